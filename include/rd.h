@@ -1,0 +1,167 @@
+/*
+ * rd.h - resistance distance by Lanczos iteration on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes r(s,t) = (e_s - e_t)^T L^+ (e_s - e_t) (paper Section 2.1,
+ * definition of resistance distance) for an undirected, connected, optionally
+ * weighted graph, with the Lanczos iteration of the paper's Algorithm 3
+ * (Section 3): a three-term Krylov recurrence on the normalised adjacency
+ * D^{-1/2} W D^{-1/2} started from (e_s/sqrt(d_s) - e_t/sqrt(d_t)), whose
+ * tridiagonal coefficients give r_hat = (1/d_s + 1/d_t) e_1^T (I - T)^{-1} e_1
+ * (Eq. approx_formula). Potentials phi = L^+ (e_s - e_t) and flows follow the
+ * electric-flow definition of Section 6.3 and line 1 of Algorithm 5.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns rd_status; nothing throws across the ABI. A handle is
+ *    not thread-safe: calls on one handle must not overlap.
+ *  - Node ids are int32 in [0, n). Edges are undirected, given once each as
+ *    (u[e], v[e]); edge ids are positions in that list.
+ *  - Inputs are copied; the caller may free them when the call returns.
+ *  - Unless RD_DEVICE_PTRS is passed, every pointer argument is host memory.
+ *    With RD_DEVICE_PTRS, array arguments (edge lists, weights, pair lists,
+ *    result arrays, gradients) are device pointers on the handle's device
+ *    (for instance torch CUDA tensors' data_ptr()).
+ *  - Work is enqueued on rd_options.stream (a hipStream_t; NULL means the
+ *    handle's own stream). Every call returns only after its outputs are
+ *    written (it synchronises that stream).
+ *  - Errors: RD_E_ARG for invalid arguments (ids out of range, self-loops,
+ *    duplicate edges, non-finite or non-positive weights, bad sizes),
+ *    RD_E_NOT_CONNECTED for a disconnected graph, RD_E_OOM when device memory
+ *    runs out, RD_E_DEVICE for a HIP runtime failure. rd_last_error(g) then
+ *    holds a message. Per-query outcomes are reported in rd_result.status.
+ */
+#ifndef RD_H_
+#define RD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rd_graph_s *rd_graph; /* opaque handle, owned by the library */
+
+typedef enum {
+  RD_OK = 0,
+  RD_E_ARG = 1,
+  RD_E_NOT_CONNECTED = 2,
+  RD_E_OOM = 3,
+  RD_E_DEVICE = 4,
+  RD_E_NOT_CONVERGED = 5, /* per query: iteration cap reached; r holds the last estimate */
+  RD_E_BREAKDOWN = 6      /* per query: non-positive pivot or non-finite value; r holds the last good estimate */
+} rd_status;
+
+/* flags */
+#define RD_DEVICE_PTRS 0x1u
+
+/* weight / vector dtypes */
+#define RD_F64 0
+#define RD_F32 1
+
+typedef struct {
+  int32_t precision;   /* RD_F64: vectors and sparse products in FP64.
+                          RD_F32: vectors and sparse products in FP32 with FP32
+                          accumulation; inner products summed in FP64; the
+                          Lanczos scalars and the tridiagonal solve in FP64. */
+  int32_t max_iters;   /* iteration cap; 0 = min(n, 100000) */
+  int32_t fixed_k;     /* > 0: run exactly k iterations, as Algorithm 3 states
+                          it (eps is ignored; an exact breakdown still stops) */
+  int32_t delay;       /* window d of the stopping estimator; 0 = 4 */
+  int32_t block_width; /* rd_query_batch: columns per sweep, 0 = autotuned */
+  int32_t err_mode;    /* 0: eps is relative to r_hat; 1: eps is absolute
+                          (the paper's error notion, Definition of
+                          epsilon-absolute error) */
+  uint32_t flags;      /* RD_DEVICE_PTRS: the array arguments of rd_query_batch
+                          and rd_grad_edges are device pointers */
+  void *stream;        /* hipStream_t, NULL = the handle's stream */
+} rd_options;
+
+typedef struct {
+  double r;       /* r_hat(s,t) */
+  double err_est; /* stopping estimate of r - r_hat (absolute) */
+  int32_t iters;  /* Lanczos iterations performed */
+  int32_t status; /* RD_OK, RD_E_NOT_CONVERGED or RD_E_BREAKDOWN */
+} rd_result;
+
+/* Fill *o with the defaults (FP64, eps relative, delay 4, autotuned width). */
+void rd_default_options(rd_options *o);
+
+/*
+ * Build a graph handle on the current HIP device.
+ *  n        number of nodes (>= 2)
+ *  m        number of undirected edges (>= 1)
+ *  u, v     int32[m] endpoints of edge e (u[e] != v[e]; each pair at most once)
+ *  w        weights[m] of dtype w_dtype (RD_F64 or RD_F32), finite and > 0;
+ *           NULL means unit weights (the unweighted graphs the paper focuses on,
+ *           Section 2.1; weighted graphs by the direct generalisation stated there)
+ *  flags    RD_DEVICE_PTRS if u, v, w are device pointers
+ *  out      receives the handle (NULL on failure)
+ * Builds the symmetric CSR, weighted degrees d_u = sum_v w_uv in FP64 and the
+ * launch schedule on the device; checks connectivity (RD_E_NOT_CONNECTED).
+ */
+rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
+                        int32_t w_dtype, uint32_t flags, rd_graph *out);
+
+/* Replace the edge weights (same edge list order, same rules as rd_init_graph). */
+rd_status rd_set_weights(rd_graph g, const void *w, int32_t w_dtype, uint32_t flags);
+
+/* n, m and the number of stored adjacency entries (2m). Any pointer may be NULL. */
+rd_status rd_graph_info(rd_graph g, int32_t *n, int64_t *m, int64_t *nnz);
+
+/*
+ * One pair, the plain single-pair loop (Algorithm 3). s == t gives r = 0 with
+ * iters = 0. eps > 0 is the stopping tolerance (relative unless
+ * o->err_mode = 1) unless o->fixed_k > 0. o may be NULL (defaults).
+ * out is host memory (RD_DEVICE_PTRS is not accepted here).
+ */
+rd_status rd_query(rd_graph g, int32_t s, int32_t t, double eps, const rd_options *o,
+                   rd_result *out);
+
+/*
+ * Diagnostic form of rd_query: runs exactly k iterations (stopping early only
+ * at an exact breakdown) and writes, for i = 1..iters, alpha_i, beta_{i+1} and
+ * r_hat_i to alpha[i-1], beta[i-1], rhat[i-1] (host arrays of length k).
+ * *iters receives the number of iterations performed.
+ */
+rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_options *o,
+                         double *alpha, double *beta, double *rhat, int32_t *iters);
+
+/*
+ * Many pairs: npairs independent Lanczos runs advanced together as block
+ * columns of one sparse product per iteration; a column that meets eps is
+ * retired and its slot refilled with the next pending pair. s, t are int32[npairs]
+ * and out rd_result[npairs]; all three are device pointers when o->flags has
+ * RD_DEVICE_PTRS.
+ */
+rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
+                         double eps, const rd_options *o, rd_result *out);
+
+/*
+ * Edge-weight gradient of L = sum_p grad_r[p] r(s_p, t_p):
+ *   grad_w[e] = -sum_p grad_r[p] (phi_p(u_e) - phi_p(v_e))^2,
+ * with phi_p = L^+ (e_s - e_t) estimated as in line 1 of Algorithm 5 from the
+ * same Lanczos run that gives r_hat. grad_r may be NULL (all ones). fwd, when
+ * not NULL, receives the forward results (rd_result[npairs]). grad_w is
+ * float[m] in edge-list order. When o->flags has RD_DEVICE_PTRS, s, t,
+ * grad_r, fwd and grad_w are device pointers.
+ */
+rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
+                        const double *grad_r, double eps, const rd_options *o, rd_result *fwd,
+                        float *grad_w);
+
+/* Release the handle and its device memory. NULL is ignored. */
+void rd_free_graph(rd_graph g);
+
+/* Static description of a status code. */
+const char *rd_status_string(rd_status s);
+
+/* Message of the last failing call on g (empty if none); valid until the next
+ * call on g. With g == NULL: the message of this thread's last failed
+ * rd_init_graph. */
+const char *rd_last_error(rd_graph g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RD_H_ */

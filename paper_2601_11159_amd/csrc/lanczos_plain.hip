@@ -1,0 +1,346 @@
+// Single-pair Lanczos iteration (Algorithm 3) on the device.
+//
+// Vectors are kept in the degree-scaled basis q_i = D^{-1/2} v_i. The
+// recurrence of Eq. lz_recurrence, beta_{i+1} v_{i+1} = (calA - alpha_i) v_i -
+// beta_i v_{i-1} with calA = D^{-1/2} W D^{-1/2}, becomes
+//     beta_{i+1} q_{i+1} = (D^{-1} W - alpha_i) q_i - beta_i q_{i-1},
+// and the inner products <x, y> of v-vectors become sum_u d_u x_u y_u. The
+// alpha_i, beta_i, T and r_hat are identical; for unit weights the product
+// needs no stored matrix values and no per-entry scale factors.
+//
+// Each vector is stored unnormalised together with a scale (q_i = sig * U_i),
+// so the division by beta_{i+1} is applied when the vector is next read.
+//
+// One iteration = four launches on one stream:
+//   k_spmv          y = sig_i D^{-1} W U_i - beta_i q_{i-1}   (+ per-block <y, q_i>_D)
+//   k_reduce_alpha  alpha_i, LDL^T update of I - T_i, r_hat_i, stopping test
+//   k_update        w = y - alpha_i q_i                       (+ per-block ||w||_D^2)
+//   k_reduce_beta   beta_{i+1}, breakdown test, next scales
+// Every kernel returns at once when the run has stopped, so the host may
+// enqueue iterations ahead of the stopping decision.
+
+#include <algorithm>
+#include <vector>
+
+#include "lanczos_common.h"
+
+namespace {
+
+constexpr int SPMV_THREADS = 256;
+constexpr int BLOCK_NNZ = 2048;  // adjacency entries staged per multi-row block
+constexpr int UPD_THREADS = 256;
+constexpr int RED_THREADS = 1024;
+
+template <typename VT>
+struct VecTraits;
+template <>
+struct VecTraits<double> {
+  static const double *w(rd_graph g) { return g->w64; }
+  static const double *invdeg(rd_graph g) { return g->invdeg; }
+};
+template <>
+struct VecTraits<float> {
+  static const float *w(rd_graph g) { return g->w32; }
+  static const float *invdeg(rd_graph g) { return g->invdeg32; }
+};
+
+// y_u = sig (1/d_u) sum_v w_uv U_cur[v] - prev_coef U_prev[u], written over
+// U_prev[u]; per-block partial of sum_u d_u y_u (sig U_cur[u]).
+template <typename VT, bool WEIGHTED>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
+    const int32_t *__restrict__ blk_row, const int8_t *__restrict__ blk_lanes,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const VT *__restrict__ w, const VT *__restrict__ invdeg, const double *__restrict__ deg,
+    const VT *__restrict__ Ucur, VT *__restrict__ Y, double *__restrict__ part,
+    const LzState *__restrict__ st) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ VT vals[BLOCK_NNZ];
+  __shared__ double red[SPMV_THREADS / 64];
+  __shared__ VT vred[SPMV_THREADS / 64];
+  const double sigd = st->sig_cur, pcd = st->prev_coef;
+  const VT sig = (VT)sigd, pc = (VT)pcd;
+  const bool has_prev = pcd != 0.0;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int32_t r0 = blk_row[b], r1 = blk_row[b + 1];
+  const int lg = blk_lanes[b];
+  const int32_t p0 = row_ptr[r0], p1 = row_ptr[r1];
+  double apart = 0.0;
+  if (lg < 0) {
+    VT acc = 0;
+    for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
+      VT x = Ucur[col[p]];
+      acc += WEIGHTED ? w[p] * x : x;
+    }
+    acc = block_sum(acc, vred);
+    if (tid == 0) {
+      VT y = sig * acc * invdeg[r0];
+      if (has_prev) y -= pc * Y[r0];
+      Y[r0] = y;
+      apart = deg[r0] * (double)y * ((double)sig * (double)Ucur[r0]);
+    }
+  } else {
+    for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
+      VT x = Ucur[col[p]];
+      vals[p - p0] = WEIGHTED ? w[p] * x : x;
+    }
+    __syncthreads();
+    const int gsz = 1 << lg, lane = tid & (gsz - 1);
+    const int ngrp = SPMV_THREADS >> lg;
+    for (int32_t r = r0 + (tid >> lg); r < r1; r += ngrp) {
+      const int32_t qb = row_ptr[r] - p0, qe = row_ptr[r + 1] - p0;
+      VT acc = 0;
+      for (int32_t q = qb + lane; q < qe; q += gsz) acc += vals[q];
+      for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, gsz);
+      if (lane == 0) {
+        VT y = sig * acc * invdeg[r];
+        if (has_prev) y -= pc * Y[r];
+        Y[r] = y;
+        apart += deg[r] * (double)y * ((double)sig * (double)Ucur[r]);
+      }
+    }
+  }
+  apart = block_sum(apart, red);
+  if (tid == 0) part[b] = apart;
+}
+
+// Fixed-order sum of nb partials by one block.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb, double *sm) {
+  double a = 0.0;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) a += part[j];
+  return block_sum(a, sm);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_alpha(const double *__restrict__ part, int nb,
+                                                              LzState *__restrict__ st,
+                                                              double *tr_alpha, double *tr_rhat) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ double sm[RED_THREADS / 64];
+  const double a = sum_partials(part, nb, sm);
+  if (threadIdx.x == 0) {
+    LzState S = *st;
+    scalar_after_alpha(S, a, tr_alpha, tr_rhat);
+    *st = S;
+  }
+}
+
+// w = y - alpha_i sig_i U_cur, in place over y; per-block partial of sum d w^2.
+template <typename VT>
+__global__ __launch_bounds__(UPD_THREADS) void k_update(int32_t n, const double *__restrict__ deg,
+                                                        const VT *__restrict__ Ucur,
+                                                        VT *__restrict__ Y, double *__restrict__ part,
+                                                        const LzState *__restrict__ st) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ double red[UPD_THREADS / 64];
+  const VT a = (VT)(st->alpha * st->sig_cur);
+  double acc = 0.0;
+  for (int32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < n; i += gridDim.x * UPD_THREADS) {
+    VT x = Y[i] - a * Ucur[i];
+    Y[i] = x;
+    acc += deg[i] * ((double)x * (double)x);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(const double *__restrict__ part, int nb,
+                                                             LzState *__restrict__ st,
+                                                             double *tr_beta) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ double sm[RED_THREADS / 64];
+  const double bb = sum_partials(part, nb, sm);
+  if (threadIdx.x == 0) {
+    LzState S = *st;
+    scalar_after_beta(S, bb, tr_beta);
+    *st = S;
+  }
+}
+
+// q_1 = (e_s/d_s - e_t/d_t)/sqrt(c), c = 1/d_s + 1/d_t (v_1 of Algorithm 3 in the scaled basis).
+template <typename VT>
+__global__ void k_init(int32_t n, VT *__restrict__ U, const double *__restrict__ deg, int32_t s,
+                       int32_t t, double tol, int32_t max_iters, int32_t fixed_k, int32_t delay,
+                       int32_t err_mode, LzState *__restrict__ st) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double c = 1.0 / deg[s] + 1.0 / deg[t];
+    const double rc = 1.0 / sqrt(c);
+    double x = 0.0;
+    if (i == s) x = rc / deg[s];
+    if (i == t) x = -rc / deg[t];
+    U[i] = (VT)x;
+    if (i == 0) {
+      LzState S;
+      state_start(S, s, t, c, tol, max_iters, fixed_k, delay, err_mode, 0);
+      *st = S;
+    }
+  }
+}
+
+}  // namespace
+
+struct PlainWork {
+  int32_t n = 0;
+  void *U[2] = {nullptr, nullptr};  // n doubles each (room for either precision)
+  double *part = nullptr;
+  int32_t npart = 0;
+  LzState *st = nullptr;
+  LzState *st_host = nullptr;  // pinned
+  int upd_blocks = 0;
+  int last_k = 8;  // iterations of the previous query: first chunk size
+};
+
+void plain_free(rd_graph g) {
+  PlainWork *pw = g->plain;
+  if (!pw) return;
+  dev_free(pw->U[0]);
+  dev_free(pw->U[1]);
+  dev_free(pw->part);
+  dev_free(pw->st);
+  if (pw->st_host) (void)hipHostFree(pw->st_host);
+  delete pw;
+  g->plain = nullptr;
+}
+
+static PlainWork *plain_get(rd_graph g) {
+  if (g->plain) return g->plain;
+  PlainWork *pw = new PlainWork();
+  try {
+    pw->n = g->n;
+    pw->U[0] = dev_alloc((size_t)g->n * sizeof(double));
+    pw->U[1] = dev_alloc((size_t)g->n * sizeof(double));
+    int dev_cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+    pw->upd_blocks = std::max(1, std::min<int>((g->n + UPD_THREADS * 4 - 1) / (UPD_THREADS * 4),
+                                               dev_cus * 8));
+    pw->npart = std::max(g->nblk, pw->upd_blocks);
+    pw->part = (double *)dev_alloc((size_t)pw->npart * sizeof(double));
+    pw->st = (LzState *)dev_alloc(sizeof(LzState));
+    RD_HIP(hipHostMalloc((void **)&pw->st_host, sizeof(LzState), hipHostMallocDefault));
+  } catch (...) {
+    g->plain = pw;
+    plain_free(g);
+    throw;
+  }
+  g->plain = pw;
+  return pw;
+}
+
+template <typename VT>
+static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st, double *tr_alpha,
+                              double *tr_beta, double *tr_rhat) {
+  const VT *Ucur = (const VT *)pw->U[cur];
+  VT *Y = (VT *)pw->U[1 - cur];
+  if (g->unit)
+    hipLaunchKernelGGL((k_spmv<VT, false>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
+                       g->blk_lanes, g->row_ptr, g->col, (const VT *)nullptr,
+                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Y, pw->part, pw->st);
+  else
+    hipLaunchKernelGGL((k_spmv<VT, true>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
+                       g->blk_lanes, g->row_ptr, g->col, VecTraits<VT>::w(g),
+                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Y, pw->part, pw->st);
+  hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(RED_THREADS), 0, st, pw->part, g->nblk, pw->st,
+                     tr_alpha, tr_rhat);
+  hipLaunchKernelGGL(k_update<VT>, dim3(pw->upd_blocks), dim3(UPD_THREADS), 0, st, g->n, g->deg,
+                     Ucur, Y, pw->part, pw->st);
+  hipLaunchKernelGGL(k_reduce_beta, dim3(1), dim3(RED_THREADS), 0, st, pw->part, pw->upd_blocks,
+                     pw->st, tr_beta);
+}
+
+template <typename VT>
+static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o,
+                        hipStream_t st, rd_result *out, double *tr_alpha, double *tr_beta,
+                        double *tr_rhat) {
+  PlainWork *pw = plain_get(g);
+  hipLaunchKernelGGL(k_init<VT>, dim3((g->n + 255) / 256), dim3(256), 0, st, g->n, (VT *)pw->U[0],
+                     g->deg, s, t, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, pw->st);
+  RD_HIP(hipGetLastError());
+  const int cap = o.fixed_k > 0 ? o.fixed_k : o.max_iters;
+  int done_iters = 0, cur = 0;
+  int chunk = o.fixed_k > 0 ? o.fixed_k : std::max(4, std::min(pw->last_k, 64));
+  for (;;) {
+    const int todo = std::min(chunk, cap - done_iters);
+    for (int j = 0; j < todo; ++j) {
+      enqueue_iteration<VT>(g, pw, cur, st, tr_alpha, tr_beta, tr_rhat);
+      cur ^= 1;
+    }
+    RD_HIP(hipGetLastError());
+    done_iters += todo;
+    RD_HIP(hipMemcpyAsync(pw->st_host, pw->st, sizeof(LzState), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    if (pw->st_host->status != LZ_RUNNING || done_iters >= cap) break;
+    chunk = std::min(2 * chunk, 256);
+  }
+  const LzState &S = *pw->st_host;
+  int32_t status = S.status;
+  if (status == LZ_RUNNING) status = LZ_NOT_CONVERGED;  // cap reached while still running
+  out->r = S.rhat;
+  out->err_est = S.err_est;
+  out->iters = S.k;
+  out->status = status_of(status);
+  pw->last_k = std::max(4, S.k);
+}
+
+void plain_run(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o, hipStream_t st,
+               rd_result *out, double *tr_alpha, double *tr_beta, double *tr_rhat, int32_t) {
+  if (o.precision == RD_F64)
+    plain_run_t<double>(g, s, t, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
+  else
+    plain_run_t<float>(g, s, t, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
+}
+
+extern "C" {
+
+rd_status rd_query(rd_graph g, int32_t s, int32_t t, double eps, const rd_options *o,
+                   rd_result *out) {
+  if (!g || !out) return RD_E_ARG;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    RD_REQUIRE(s >= 0 && s < g->n && t >= 0 && t < g->n, "s and t must be in [0, n)");
+    RD_REQUIRE(opt.fixed_k > 0 || eps > 0.0, "eps must be > 0 unless fixed_k is set");
+    if (s == t) {
+      *out = rd_result{0.0, 0.0, 0, RD_OK};
+      return RD_OK;
+    }
+    RD_HIP(hipSetDevice(g->device));
+    plain_run(g, s, t, eps, opt, pick_stream(g, o), out, nullptr, nullptr, nullptr, 0);
+    return RD_OK;
+  } catch (const RdError &e) {
+    g->err = e.msg;
+    return e.code;
+  }
+}
+
+rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_options *o,
+                         double *alpha, double *beta, double *rhat, int32_t *iters) {
+  if (!g || !alpha || !beta || !rhat || !iters || k < 1) return RD_E_ARG;
+  double *dtr = nullptr;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    RD_REQUIRE(s >= 0 && s < g->n && t >= 0 && t < g->n && s != t, "need s != t in [0, n)");
+    opt.fixed_k = k;
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, o);
+    dtr = (double *)dev_alloc(3 * (size_t)k * sizeof(double));
+    RD_HIP(hipMemsetAsync(dtr, 0, 3 * (size_t)k * sizeof(double), st));
+    rd_result res;
+    plain_run(g, s, t, 1.0, opt, st, &res, dtr, dtr + k, dtr + 2 * k, k);
+    std::vector<double> h(3 * (size_t)k);
+    RD_HIP(hipMemcpyAsync(h.data(), dtr, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    std::copy(h.begin(), h.begin() + k, alpha);
+    std::copy(h.begin() + k, h.begin() + 2 * k, beta);
+    std::copy(h.begin() + 2 * k, h.end(), rhat);
+    *iters = res.iters;
+    dev_free(dtr);
+    return RD_OK;
+  } catch (const RdError &e) {
+    dev_free(dtr);
+    g->err = e.msg;
+    return e.code;
+  }
+}
+
+}  // extern "C"
