@@ -124,10 +124,11 @@ inline unsigned grid_for(int64_t work, int threads) {
   return (unsigned)((work + threads - 1) / threads);
 }
 
-// Row blocks for the single-pair SpMV: consecutive rows whose adjacency
-// entries total at most `budget`, or one row alone when it is longer. Each
+// Row blocks for the single-pair SpMV: at most `max_rows` consecutive rows
+// whose adjacency entries total at most `budget`, or one row alone when it is
+// longer. Each
 // multi-row block records log2 of the lanes that cooperate on one row.
-void build_row_blocks(rd_graph g, const std::vector<int32_t> &rp, int32_t budget) {
+void build_row_blocks(rd_graph g, const std::vector<int32_t> &rp, int32_t budget, int32_t max_rows) {
   std::vector<int32_t> start;
   std::vector<int8_t> lanes;
   const int32_t n = g->n;
@@ -142,7 +143,7 @@ void build_row_blocks(rd_graph g, const std::vector<int32_t> &rp, int32_t budget
       continue;
     }
     int32_t r1 = r + 1;
-    while (r1 < n && rp[r1 + 1] - rp[r] <= budget) ++r1;
+    while (r1 < n && r1 - r < max_rows && rp[r1 + 1] - rp[r] <= budget) ++r1;
     int32_t rows = r1 - r;
     int32_t avg = (rp[r1] - rp[r]) / rows;
     int lg = 0;
@@ -455,7 +456,7 @@ rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v
 
     std::vector<int32_t> rp(n + 1);
     RD_HIP(hipMemcpy(rp.data(), g->row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    build_row_blocks(g, rp, 2048);
+    build_row_blocks(g, rp, 2048, 1024);  // must match the SpMV's LDS staging limits
 
     for (void *p : owned) dev_free(p);
     owned.clear();

@@ -1,14 +1,805 @@
-// Batched Lanczos iteration: placeholder until the block-column path lands.
+// Batched Lanczos iteration: many (s,t) pairs advanced together.
+//
+// B independent runs of Algorithm 3 share one pass over the graph per
+// iteration. The vectors of all runs form n x B row-major blocks (column j =
+// slot j), so the sparse product reads each neighbour row X[v, 0:B] as one
+// contiguous segment (B FP32 values = B*4 bytes) instead of B scattered words.
+// The runs are independent (no coupling between columns); each column keeps its
+// own FP64 scalars, tridiagonal solve and stopping test. A column whose run
+// stops is retired and refilled with the next pending pair in the same
+// iteration, so slots stay busy while pairs of uneven length stream through.
+//
+// Vectors use the degree-scaled basis q = D^{-1/2} v and scale-on-read
+// normalisation as in the single-pair path (see lanczos_plain.hip).
+//
+// One iteration:
+//   k_spmm_short / k_spmm_long   Y = sig D^{-1} W U_cur - pc U_prev (+ per-block <Y, q>_D per column)
+//   k_col_sum                    alpha_j for every column
+//   k_control                    scalar update, stopping test, retire + refill (one block, fixed order)
+//   k_update                     W = Y - alpha sig U_cur, or the start vector of a refilled column
+//   k_col_sum + k_beta           beta_{j, i+1} and next scales
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "lanczos_common.h"
 
-void batch_free(rd_graph g) { (void)g; }
+namespace {
+
+constexpr int SHORT_THREADS = 256;
+constexpr int LONG_THREADS = 1024;
+constexpr int LONG_DEG = 1024;   // rows longer than this go to the split-row kernel
+constexpr int WAVE_NNZ = 256;    // adjacency entries per wave work item (short rows)
+constexpr int COL_THREADS = 256;
+
+enum : int32_t { COL_RUN = 0, COL_REFILL = 1, COL_IDLE = 2 };
+
+struct ColCtrl {
+  double sig;   // q = sig * U_cur[:, j]
+  double pc;    // coefficient of U_prev[:, j] (0: the previous vector is not used)
+  double coef;  // alpha * sig for the update
+  double vs;    // start vector entries of a refilled column at rows s and t
+  double vt;
+  int32_t mode;  // COL_*
+  int32_t s, t;
+  int32_t pad;
+};
+
+template <typename VT, int N>
+struct alignas(sizeof(VT) * N) VecN {
+  VT v[N];
+};
+
+template <typename VT, int N>
+__device__ __forceinline__ VecN<VT, N> vload(const VT *p) {
+  return *reinterpret_cast<const VecN<VT, N> *>(p);
+}
+template <typename VT, int N>
+__device__ __forceinline__ void vstore(VT *p, const VecN<VT, N> &x) {
+  *reinterpret_cast<VecN<VT, N> *>(p) = x;
+}
+
+template <int B>
+struct Shape {
+  static constexpr int VEC = B >= 64 ? B / 64 : 1;  // columns per lane
+  static constexpr int LPR = B / VEC;               // lanes per row
+  static constexpr int RPW = 64 / LPR;              // rows per wavefront
+};
+
+// Fold the per-lane column partials of all rows handled by a block into
+// part[j * ldp + slot] (fixed order: sub-rows of a wave, then waves).
+template <int B, int VEC>
+__device__ __forceinline__ void block_column_partials(double (&apart)[VEC], double *sm, double *part,
+                                                      int32_t ldp, int32_t slot) {
+  using S = Shape<B>;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int v = 0; v < VEC; ++v)
+    for (int off = S::LPR; off < 64; off <<= 1) apart[v] += __shfl_xor(apart[v], off, 64);
+  if (lane < S::LPR) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) sm[wid * B + lane * VEC + v] = apart[v];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    double a = 0.0;
+    for (int w = 0; w < nw; ++w) a += sm[w * B + j];
+    part[(size_t)j * ldp + slot] = a;
+  }
+}
+
+// Rows of length <= LONG_DEG. Wave work items are contiguous row ranges of
+// bounded adjacency length; items are dealt to wavefronts round-robin (a fixed
+// assignment, so the partial sums do not depend on timing).
+template <typename VT, int B, bool WEIGHTED>
+__global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
+    int32_t nwi, const int32_t *__restrict__ witem_row, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
+    const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
+    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp) {
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  using V = VecN<VT, VEC>;
+  __shared__ double sm[(SHORT_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  VT sig[VEC], pc[VEC];
+  bool hp[VEC];
+  double apart[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    sig[v] = (VT)ctrl[c0 + v].sig;
+    pc[v] = (VT)ctrl[c0 + v].pc;
+    hp[v] = ctrl[c0 + v].pc != 0.0;
+    apart[v] = 0.0;
+  }
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t it = gw; it < nwi; it += nwv) {
+    const int32_t rb = witem_row[it], re = witem_row[it + 1];
+    for (int32_t r = rb + sub; r < re; r += S::RPW) {
+      const int32_t pb = row_ptr[r], pe = row_ptr[r + 1];
+      if (pe - pb > LONG_DEG) continue;
+      VT acc[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] = 0;
+      int32_t p = pb;
+      for (; p + 8 <= pe; p += 8) {
+        int32_t ci[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ci[k] = col[p + k];
+        V x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = vload<VT, VEC>(Ucur + (size_t)ci[k] * B + c0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const VT wk = WEIGHTED ? w[p + k] : VT(1);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] += WEIGHTED ? wk * x[k].v[v] : x[k].v[v];
+        }
+      }
+      for (; p < pe; ++p) {
+        const V x = vload<VT, VEC>(Ucur + (size_t)col[p] * B + c0);
+        const VT wk = WEIGHTED ? w[p] : VT(1);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += WEIGHTED ? wk * x.v[v] : x.v[v];
+      }
+      const VT id = invdeg[r];
+      const double dr = deg[r];
+      const V up = vload<VT, VEC>(Y + (size_t)r * B + c0);
+      const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
+      V y;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        VT yy = sig[v] * acc[v] * id;
+        if (hp[v]) yy -= pc[v] * up.v[v];
+        y.v[v] = yy;
+        apart[v] += dr * (double)yy * ((double)sig[v] * (double)uc.v[v]);
+      }
+      vstore<VT, VEC>(Y + (size_t)r * B + c0, y);
+    }
+  }
+  block_column_partials<B, VEC>(apart, sm, part, ldp, blockIdx.x);
+}
+
+// Rows longer than LONG_DEG: one block per row, entries split over all
+// sub-rows of the block and combined in LDS in a fixed order.
+template <typename VT, int B, bool WEIGHTED>
+__global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
+    const int32_t *__restrict__ long_rows, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
+    const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
+    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp, int32_t poff) {
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  constexpr int NG = (LONG_THREADS / 64) * S::RPW;  // sub-rows per block
+  using V = VecN<VT, VEC>;
+  __shared__ VT acc_sm[NG * B];
+  __shared__ double sm[(LONG_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  const int g = wid * S::RPW + sub;
+  const int32_t r = long_rows[blockIdx.x];
+  const int32_t pb = row_ptr[r], pe = row_ptr[r + 1];
+  VT acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0;
+  int32_t p = pb + g;
+  for (; p + 3 * NG < pe; p += 4 * NG) {
+    int32_t ci[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ci[k] = col[p + k * NG];
+    V x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = vload<VT, VEC>(Ucur + (size_t)ci[k] * B + c0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const VT wk = WEIGHTED ? w[p + k * NG] : VT(1);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += WEIGHTED ? wk * x[k].v[v] : x[k].v[v];
+    }
+  }
+  for (; p < pe; p += NG) {
+    const V x = vload<VT, VEC>(Ucur + (size_t)col[p] * B + c0);
+    const VT wk = WEIGHTED ? w[p] : VT(1);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += WEIGHTED ? wk * x.v[v] : x.v[v];
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc_sm[g * B + c0 + v] = acc[v];
+  __syncthreads();
+  double apart[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) apart[v] = 0.0;
+  if (g == 0) {
+    VT tot[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      tot[v] = 0;
+      for (int h = 0; h < NG; ++h) tot[v] += acc_sm[h * B + c0 + v];
+    }
+    const VT id = invdeg[r];
+    const double dr = deg[r];
+    const V up = vload<VT, VEC>(Y + (size_t)r * B + c0);
+    const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
+    V y;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const VT sg = (VT)ctrl[c0 + v].sig;
+      const double pcd = ctrl[c0 + v].pc;
+      VT yy = sg * tot[v] * id;
+      if (pcd != 0.0) yy -= (VT)pcd * up.v[v];
+      y.v[v] = yy;
+      apart[v] = dr * (double)yy * ((double)sg * (double)uc.v[v]);
+    }
+    vstore<VT, VEC>(Y + (size_t)r * B + c0, y);
+  }
+  block_column_partials<B, VEC>(apart, sm, part, ldp, poff + blockIdx.x);
+}
+
+// out[j] = sum_k part[j * ldp + k], k < np (block j, fixed order).
+__global__ __launch_bounds__(COL_THREADS) void k_col_sum(const double *__restrict__ part, int32_t ldp,
+                                                         int32_t np, double *__restrict__ out) {
+  __shared__ double sm[COL_THREADS / 64];
+  const double *p = part + (size_t)blockIdx.x * ldp;
+  double a = 0.0;
+  for (int k = threadIdx.x; k < np; k += COL_THREADS) a += p[k];
+  a = block_sum(a, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+struct RunParams {
+  double tol;
+  int32_t max_iters, fixed_k, delay, err_mode;
+  int32_t npairs;
+};
+
+__device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
+  rd_result r;
+  r.r = S.rhat;
+  r.err_est = S.err_est;
+  r.iters = S.k;
+  r.status = (int32_t)status_of(S.status);
+  out[S.pair] = r;
+}
+
+// Scalar step for every column after alpha, then retirement and refill in
+// column order (one block; thread 0 pops the pair queue serially so the
+// assignment of pairs to slots is deterministic).
+__global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict__ st,
+                                                 ColCtrl *__restrict__ ctrl,
+                                                 const double *__restrict__ alpha, RunParams prm,
+                                                 const int32_t *__restrict__ ps,
+                                                 const int32_t *__restrict__ pt,
+                                                 const double *__restrict__ deg,
+                                                 rd_result *__restrict__ out,
+                                                 int32_t *__restrict__ qstate) {
+  __shared__ int32_t need[256];
+  __shared__ int32_t newpair[256];
+  const int j = threadIdx.x;
+  LzState S;
+  if (j < B) {
+    S = st[j];
+    if (S.status == LZ_RUNNING) scalar_after_alpha(S, alpha[j], nullptr, nullptr);
+    const bool fin = S.status == LZ_DONE || S.status == LZ_NOT_CONVERGED || S.status == LZ_BREAKDOWN;
+    if (fin) write_result(out, S);
+    need[j] = (fin || S.status == LZ_IDLE) ? 1 : 0;
+  }
+  __syncthreads();
+  if (j == 0) {
+    int32_t head = qstate[0];
+    for (int c = 0; c < B; ++c) {
+      newpair[c] = -2;
+      if (!need[c]) continue;
+      int32_t idx = -1;
+      while (head < prm.npairs) {
+        const int32_t cand = head++;
+        if (ps[cand] == pt[cand]) {
+          out[cand] = rd_result{0.0, 0.0, 0, RD_OK};
+          continue;
+        }
+        idx = cand;
+        break;
+      }
+      newpair[c] = idx;
+    }
+    qstate[0] = head;
+  }
+  __syncthreads();
+  int32_t active = 0;
+  if (j < B) {
+    ColCtrl cc = ctrl[j];
+    const int32_t np = newpair[j];
+    if (np >= 0) {
+      const int32_t s = ps[np], t = pt[np];
+      const double c = 1.0 / deg[s] + 1.0 / deg[t];
+      state_start(S, s, t, c, prm.tol, prm.max_iters, prm.fixed_k, prm.delay, prm.err_mode, np);
+      const double rc = 1.0 / sqrt(c);
+      cc.mode = COL_REFILL;
+      cc.sig = 1.0;
+      cc.pc = 0.0;
+      cc.coef = 0.0;
+      cc.vs = rc / deg[s];
+      cc.vt = -rc / deg[t];
+      cc.s = s;
+      cc.t = t;
+      active = 1;
+    } else if (np == -1) {
+      S.status = LZ_IDLE;
+      cc.mode = COL_IDLE;
+      cc.sig = 0.0;
+      cc.pc = 0.0;
+      cc.coef = 0.0;
+    } else {
+      cc.mode = COL_RUN;
+      cc.coef = S.alpha * S.sig_cur;
+      active = 1;
+    }
+    st[j] = S;
+    ctrl[j] = cc;
+  }
+  // count active columns
+  __shared__ int32_t cnt[4];
+  int32_t a = active;
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((j & 63) == 0) cnt[j >> 6] = a;
+  __syncthreads();
+  if (j == 0) qstate[1] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// W = Y - alpha sig U_cur for running columns (in place over Y), the start
+// vector for refilled columns, zero for idle ones; per-block sum d W^2.
+template <typename VT, int B>
+__global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const double *__restrict__ deg,
+                                                          const VT *__restrict__ Ucur,
+                                                          VT *__restrict__ Y,
+                                                          const ColCtrl *__restrict__ ctrl,
+                                                          double *__restrict__ part, int32_t ldp) {
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  using V = VecN<VT, VEC>;
+  __shared__ double sm[(SHORT_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  VT coef[VEC], vs[VEC], vt[VEC];
+  int32_t mode[VEC], cs[VEC], ct[VEC];
+  double acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const ColCtrl &cc = ctrl[c0 + v];
+    coef[v] = (VT)cc.coef;
+    vs[v] = (VT)cc.vs;
+    vt[v] = (VT)cc.vt;
+    mode[v] = cc.mode;
+    cs[v] = cc.s;
+    ct[v] = cc.t;
+    acc[v] = 0.0;
+  }
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t r = gw * S::RPW + sub; r < n; r += nwv * S::RPW) {
+    const V y = vload<VT, VEC>(Y + (size_t)r * B + c0);
+    const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
+    const double dr = deg[r];
+    V o;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      VT x;
+      if (mode[v] == COL_RUN) {
+        x = y.v[v] - coef[v] * uc.v[v];
+        acc[v] += dr * ((double)x * (double)x);
+      } else if (mode[v] == COL_REFILL) {
+        x = (r == cs[v]) ? vs[v] : ((r == ct[v]) ? vt[v] : VT(0));
+      } else {
+        x = VT(0);
+      }
+      o.v[v] = x;
+    }
+    vstore<VT, VEC>(Y + (size_t)r * B + c0, o);
+  }
+  block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
+}
+
+// beta_{i+1} of every running column and the next scales.
+__global__ __launch_bounds__(COL_THREADS) void k_beta(const double *__restrict__ part, int32_t ldp,
+                                                      int32_t np, LzState *__restrict__ st,
+                                                      ColCtrl *__restrict__ ctrl) {
+  __shared__ double sm[COL_THREADS / 64];
+  const int j = blockIdx.x;
+  const double *p = part + (size_t)j * ldp;
+  double a = 0.0;
+  for (int k = threadIdx.x; k < np; k += COL_THREADS) a += p[k];
+  a = block_sum(a, sm);
+  if (threadIdx.x == 0) {
+    ColCtrl cc = ctrl[j];
+    if (cc.mode != COL_RUN) return;
+    LzState S = st[j];
+    if (S.status != LZ_RUNNING) return;
+    scalar_after_beta(S, a, nullptr);
+    cc.sig = S.sig_cur;
+    cc.pc = S.prev_coef;
+    st[j] = S;
+    ctrl[j] = cc;
+  }
+}
+
+__global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__restrict__ ctrl,
+                              int32_t *__restrict__ qstate) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < B) {
+    LzState S;
+    state_start(S, 0, 0, 0.0, 0.0, 0, 0, 4, 0, -1);
+    S.status = LZ_IDLE;
+    st[j] = S;
+    ColCtrl cc;
+    cc.sig = 0.0;
+    cc.pc = 0.0;
+    cc.coef = 0.0;
+    cc.vs = 0.0;
+    cc.vt = 0.0;
+    cc.mode = COL_IDLE;
+    cc.s = -1;
+    cc.t = -1;
+    cc.pad = 0;
+    ctrl[j] = cc;
+  }
+  if (j == 0) {
+    qstate[0] = 0;
+    qstate[1] = 0;
+  }
+}
+
+__global__ void k_check_pairs(int32_t npairs, int32_t n, const int32_t *__restrict__ s,
+                              const int32_t *__restrict__ t, int32_t *__restrict__ flag) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npairs && (s[i] < 0 || s[i] >= n || t[i] < 0 || t[i] >= n)) atomicOr(flag, 1);
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct BatchWork {
+  // schedule (independent of B and precision)
+  int32_t nwi = 0, nlong = 0;
+  int32_t *witem_row = nullptr;  // [nwi+1]
+  int32_t *long_rows = nullptr;  // [nlong]
+  int32_t grid_short = 0, grid_upd = 0;
+  // buffers sized for the widest run so far
+  size_t vec_bytes = 0;
+  void *X[2] = {nullptr, nullptr};
+  int32_t Bcap = 0;
+  double *part = nullptr;  // [Bcap][ldp]
+  int32_t ldp = 0;
+  double *colsum = nullptr;  // [Bcap]
+  LzState *st = nullptr;
+  ColCtrl *ctrl = nullptr;
+  int32_t *qstate = nullptr;       // [2]: queue head, active columns
+  int32_t *qstate_host = nullptr;  // pinned
+  int32_t *flag = nullptr;
+  // autotune cache: chosen width per precision
+  int32_t tuned[2] = {0, 0};
+};
+
+void batch_free(rd_graph g) {
+  BatchWork *bw = g->batch;
+  if (!bw) return;
+  dev_free(bw->witem_row);
+  dev_free(bw->long_rows);
+  dev_free(bw->X[0]);
+  dev_free(bw->X[1]);
+  dev_free(bw->part);
+  dev_free(bw->colsum);
+  dev_free(bw->st);
+  dev_free(bw->ctrl);
+  dev_free(bw->qstate);
+  dev_free(bw->flag);
+  if (bw->qstate_host) (void)hipHostFree(bw->qstate_host);
+  delete bw;
+  g->batch = nullptr;
+}
+
+static BatchWork *batch_get(rd_graph g) {
+  if (g->batch) return g->batch;
+  BatchWork *bw = new BatchWork();
+  g->batch = bw;
+  std::vector<int32_t> rp(g->n + 1);
+  RD_HIP(hipMemcpy(rp.data(), g->row_ptr, (g->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int32_t> items, longs;
+  items.reserve(g->nnz / WAVE_NNZ + 16);
+  int32_t r = 0;
+  while (r < g->n) {
+    items.push_back(r);
+    int64_t acc = 0;
+    while (r < g->n) {
+      const int32_t len = rp[r + 1] - rp[r];
+      if (len > LONG_DEG) {
+        longs.push_back(r);
+        ++r;
+        continue;
+      }
+      if (acc > 0 && acc + len > WAVE_NNZ) break;
+      acc += len;
+      ++r;
+    }
+  }
+  items.push_back(g->n);
+  bw->nwi = (int32_t)items.size() - 1;
+  bw->nlong = (int32_t)longs.size();
+  bw->witem_row = (int32_t *)dev_alloc(items.size() * sizeof(int32_t));
+  RD_HIP(hipMemcpy(bw->witem_row, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  bw->long_rows = (int32_t *)dev_alloc(std::max<size_t>(1, longs.size()) * sizeof(int32_t));
+  if (!longs.empty())
+    RD_HIP(hipMemcpy(bw->long_rows, longs.data(), longs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) cus = prop.multiProcessorCount;
+  // persistent-style grids: enough waves to fill the chip, a fixed count so
+  // the number of partial sums per column is fixed
+  bw->grid_short = std::max(1, std::min<int32_t>(cus * 8, (bw->nwi + 3) / 4));
+  bw->grid_upd = std::max(1, std::min<int32_t>(cus * 8, cdiv(g->n, 64)));
+  bw->ldp = std::max(bw->grid_short + bw->nlong, bw->grid_upd);
+  bw->st = (LzState *)dev_alloc(256 * sizeof(LzState));
+  bw->ctrl = (ColCtrl *)dev_alloc(256 * sizeof(ColCtrl));
+  bw->colsum = (double *)dev_alloc(256 * sizeof(double));
+  bw->qstate = (int32_t *)dev_alloc(2 * sizeof(int32_t));
+  bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
+  RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 2 * sizeof(int32_t), hipHostMallocDefault));
+  return bw;
+}
+
+static void batch_reserve(rd_graph g, BatchWork *bw, int32_t B, size_t elem) {
+  const size_t need = (size_t)g->n * B * elem;
+  if (need > bw->vec_bytes) {
+    dev_free(bw->X[0]);
+    dev_free(bw->X[1]);
+    bw->X[0] = bw->X[1] = nullptr;
+    bw->vec_bytes = 0;
+    bw->X[0] = dev_alloc(need);
+    bw->X[1] = dev_alloc(need);
+    bw->vec_bytes = need;
+  }
+  if (B > bw->Bcap) {
+    dev_free(bw->part);
+    bw->part = nullptr;
+    bw->part = (double *)dev_alloc((size_t)B * bw->ldp * sizeof(double));
+    bw->Bcap = B;
+  }
+}
+
+template <typename VT, int B, bool WEIGHTED>
+static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStream_t st) {
+  const VT *w = nullptr;
+  const VT *invdeg;
+  if constexpr (sizeof(VT) == 8) {
+    w = (const VT *)g->w64;
+    invdeg = (const VT *)g->invdeg;
+  } else {
+    w = (const VT *)g->w32;
+    invdeg = (const VT *)g->invdeg32;
+  }
+  hipLaunchKernelGGL((k_spmm_short<VT, B, WEIGHTED>), dim3(bw->grid_short), dim3(SHORT_THREADS), 0, st,
+                     bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
+                     bw->part, bw->ldp);
+  if (bw->nlong > 0)
+    hipLaunchKernelGGL((k_spmm_long<VT, B, WEIGHTED>), dim3(bw->nlong), dim3(LONG_THREADS), 0, st,
+                       bw->long_rows, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
+                       bw->part, bw->ldp, bw->grid_short);
+}
+
+template <typename VT, int B>
+static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const RunParams &prm,
+                                    const int32_t *ps, const int32_t *pt, rd_result *out,
+                                    hipStream_t st) {
+  const VT *Ucur = (const VT *)bw->X[cur];
+  VT *Y = (VT *)bw->X[1 - cur];
+  if (g->unit)
+    launch_spmm<VT, B, false>(g, bw, Ucur, Y, st);
+  else
+    launch_spmm<VT, B, true>(g, bw, Ucur, Y, st);
+  hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
+                     bw->grid_short + bw->nlong, bw->colsum);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
+  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
+                     Ucur, Y, bw->ctrl, bw->part, bw->ldp);
+  hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
+                     bw->st, bw->ctrl);
+}
+
+// Run all pairs through B slots. Returns the number of iterations enqueued.
+template <typename VT, int B>
+static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
+                           const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st) {
+  batch_reserve(g, bw, B, sizeof(VT));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
+  // fill the slots: control with every column idle pops the first B pairs,
+  // then the update writes their start vectors (and zeros elsewhere)
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
+  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
+                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp);
+  RD_HIP(hipGetLastError());
+  int cur = 0;
+  int64_t iters = 0;
+  int chunk = 4;
+  const int64_t cap = (int64_t)prm.max_iters * ((npairs + B - 1) / B + 1) + 16;
+  for (;;) {
+    for (int j = 0; j < chunk; ++j) {
+      enqueue_batch_iteration<VT, B>(g, bw, cur, prm, ps, pt, out, st);
+      cur ^= 1;
+    }
+    iters += chunk;
+    RD_HIP(hipGetLastError());
+    RD_HIP(hipMemcpyAsync(bw->qstate_host, bw->qstate, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    if (bw->qstate_host[1] == 0) break;
+    RD_REQUIRE(iters < cap, "batched run did not drain (internal error)");
+    chunk = std::min(chunk * 2, 64);
+  }
+  return iters;
+}
+
+template <typename VT>
+static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
+                              const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st) {
+  switch (B) {
+    case 16: return batch_run_t<VT, 16>(g, bw, npairs, ps, pt, prm, out, st);
+    case 32: return batch_run_t<VT, 32>(g, bw, npairs, ps, pt, prm, out, st);
+    case 64: return batch_run_t<VT, 64>(g, bw, npairs, ps, pt, prm, out, st);
+    case 128: return batch_run_t<VT, 128>(g, bw, npairs, ps, pt, prm, out, st);
+    case 256: return batch_run_t<VT, 256>(g, bw, npairs, ps, pt, prm, out, st);
+  }
+  throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
+}
+
+// Time of one sparse product at width B (vectors of arbitrary content).
+template <typename VT, int B>
+static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
+  batch_reserve(g, bw, B, sizeof(VT));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
+  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
+                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp);
+  hipEvent_t e0, e1;
+  RD_HIP(hipEventCreate(&e0));
+  RD_HIP(hipEventCreate(&e1));
+  auto once = [&]() {
+    if (g->unit) launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st);
+    else launch_spmm<VT, B, true>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st);
+  };
+  once();
+  RD_HIP(hipEventRecord(e0, st));
+  for (int k = 0; k < 3; ++k) once();
+  RD_HIP(hipEventRecord(e1, st));
+  RD_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  RD_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / 3.f;
+}
+
+template <typename VT>
+static float probe_dispatch(rd_graph g, BatchWork *bw, int32_t B, hipStream_t st) {
+  switch (B) {
+    case 16: return probe_spmm<VT, 16>(g, bw, st);
+    case 32: return probe_spmm<VT, 32>(g, bw, st);
+    case 64: return probe_spmm<VT, 64>(g, bw, st);
+    case 128: return probe_spmm<VT, 128>(g, bw, st);
+    case 256: return probe_spmm<VT, 256>(g, bw, st);
+  }
+  return 1e30f;
+}
+
+static std::string tune_key(rd_graph g, int prec) {
+  std::ostringstream k;
+  k << "n=" << g->n << ",nnz=" << g->nnz << ",maxdeg=" << g->max_deg << ",w=" << (g->unit ? 0 : 1)
+    << ",prec=" << prec;
+  return k.str();
+}
+
+// Width with the least sparse-product time per column among the candidates
+// that fit the number of pairs; remembered per handle and, when the
+// RD_AUTOTUNE_CACHE environment variable names a file, across processes.
+static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npairs, hipStream_t st) {
+  if (bw->tuned[prec]) return bw->tuned[prec];
+  const char *path = std::getenv("RD_AUTOTUNE_CACHE");
+  const std::string key = tune_key(g, prec);
+  if (path) {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const auto sp = line.rfind(' ');
+      if (sp != std::string::npos && line.substr(0, sp) == key) {
+        const int32_t B = std::atoi(line.c_str() + sp + 1);
+        if (B == 16 || B == 32 || B == 64 || B == 128 || B == 256) return bw->tuned[prec] = B;
+      }
+    }
+  }
+  int32_t best = 0;
+  double best_t = 1e300;
+  for (int32_t B : {32, 64, 128, 256}) {
+    if (B > 32 && B / 2 >= npairs) break;  // wider than the work: no gain
+    const float ms = prec == RD_F64 ? probe_dispatch<double>(g, bw, B, st) : probe_dispatch<float>(g, bw, B, st);
+    const double per_col = ms / B;
+    if (per_col < best_t) {
+      best_t = per_col;
+      best = B;
+    }
+  }
+  bw->tuned[prec] = best;
+  if (path) {
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << best << "\n";
+  }
+  return best;
+}
 
 extern "C" {
 
-rd_status rd_query_batch(rd_graph g, int32_t, const int32_t *, const int32_t *, double,
-                         const rd_options *, rd_result *) {
-  if (g) g->err = "rd_query_batch is not available in this build";
-  return RD_E_ARG;
+rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, double eps,
+                         const rd_options *o, rd_result *out) {
+  if (!g || npairs < 0 || (npairs > 0 && (!s || !t || !out))) return RD_E_ARG;
+  std::vector<void *> owned;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    RD_REQUIRE(opt.fixed_k > 0 || eps > 0.0, "eps must be > 0 unless fixed_k is set");
+    if (npairs == 0) return RD_OK;
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, o);
+    BatchWork *bw = batch_get(g);
+    const bool dp = opt.flags & RD_DEVICE_PTRS;
+    const int32_t *ds = s, *dt = t;
+    rd_result *dout = out;
+    if (!dp) {
+      int32_t *tmp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(tmp);
+      RD_HIP(hipMemcpyAsync(tmp, s, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      RD_HIP(hipMemcpyAsync(tmp + npairs, t, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      ds = tmp;
+      dt = tmp + npairs;
+      dout = (rd_result *)dev_alloc((size_t)npairs * sizeof(rd_result));
+      owned.push_back(dout);
+    }
+    RD_HIP(hipMemsetAsync(bw->flag, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->n, ds, dt,
+                       bw->flag);
+    int32_t bad = 0;
+    RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+    int32_t B = opt.block_width;
+    if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
+    RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
+               "block_width must be 0 or one of 16, 32, 64, 128, 256");
+    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
+    if (opt.precision == RD_F64)
+      batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st);
+    else
+      batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st);
+    if (!dp) {
+      RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
+    }
+    RD_HIP(hipStreamSynchronize(st));
+    for (void *p : owned) dev_free(p);
+    return RD_OK;
+  } catch (const RdError &e) {
+    (void)hipDeviceSynchronize();
+    for (void *p : owned) dev_free(p);
+    g->err = e.msg;
+    return e.code;
+  }
 }
 
 rd_status rd_grad_edges(rd_graph g, int32_t, const int32_t *, const int32_t *, const double *,

@@ -137,7 +137,7 @@ __device__ __forceinline__ void state_start(LzState &S, int32_t s, int32_t t, do
   S.pair = pair;
 }
 
-inline rd_status status_of(int32_t st) {
+__host__ __device__ inline rd_status status_of(int32_t st) {
   switch (st) {
     case LZ_DONE: return RD_OK;
     case LZ_NOT_CONVERGED: return RD_E_NOT_CONVERGED;

@@ -27,7 +27,8 @@
 namespace {
 
 constexpr int SPMV_THREADS = 256;
-constexpr int BLOCK_NNZ = 2048;  // adjacency entries staged per multi-row block
+constexpr int BLOCK_NNZ = 2048;   // adjacency entries staged per multi-row block
+constexpr int BLOCK_ROWS = 1024;  // rows per multi-row block (the schedule guarantees it)
 constexpr int UPD_THREADS = 256;
 constexpr int RED_THREADS = 1024;
 
@@ -46,6 +47,12 @@ struct VecTraits<float> {
 
 // y_u = sig (1/d_u) sum_v w_uv U_cur[v] - prev_coef U_prev[u], written over
 // U_prev[u]; per-block partial of sum_u d_u y_u (sig U_cur[u]).
+//
+// Multi-row blocks run in three phases so no global load sits on a serial
+// chain: (1) stage the block's row offsets and the gathered products
+// w_uv U_cur[v] in LDS with coalesced index loads; (2) groups of 2^lanes
+// threads reduce rows from LDS in a fixed order; (3) one thread per row applies
+// the recurrence with coalesced per-row loads and stores.
 template <typename VT, bool WEIGHTED>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     const int32_t *__restrict__ blk_row, const int8_t *__restrict__ blk_lanes,
@@ -55,6 +62,8 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     const LzState *__restrict__ st) {
   if (st->status != LZ_RUNNING) return;
   __shared__ VT vals[BLOCK_NNZ];
+  __shared__ VT rsum[BLOCK_ROWS];
+  __shared__ int32_t rp[BLOCK_ROWS + 1];
   __shared__ double red[SPMV_THREADS / 64];
   __shared__ VT vred[SPMV_THREADS / 64];
   const double sigd = st->sig_cur, pcd = st->prev_coef;
@@ -63,9 +72,9 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
   const int b = blockIdx.x, tid = threadIdx.x;
   const int32_t r0 = blk_row[b], r1 = blk_row[b + 1];
   const int lg = blk_lanes[b];
-  const int32_t p0 = row_ptr[r0], p1 = row_ptr[r1];
   double apart = 0.0;
   if (lg < 0) {
+    const int32_t p0 = row_ptr[r0], p1 = row_ptr[r0 + 1];
     VT acc = 0;
     for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
       VT x = Ucur[col[p]];
@@ -79,6 +88,10 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
       apart = deg[r0] * (double)y * ((double)sig * (double)Ucur[r0]);
     }
   } else {
+    const int32_t nrows = r1 - r0;
+    for (int32_t j = tid; j <= nrows; j += SPMV_THREADS) rp[j] = row_ptr[r0 + j];
+    __syncthreads();
+    const int32_t p0 = rp[0], p1 = rp[nrows];
     for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
       VT x = Ucur[col[p]];
       vals[p - p0] = WEIGHTED ? w[p] * x : x;
@@ -86,17 +99,20 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     __syncthreads();
     const int gsz = 1 << lg, lane = tid & (gsz - 1);
     const int ngrp = SPMV_THREADS >> lg;
-    for (int32_t r = r0 + (tid >> lg); r < r1; r += ngrp) {
-      const int32_t qb = row_ptr[r] - p0, qe = row_ptr[r + 1] - p0;
+    for (int32_t j = tid >> lg; j < nrows; j += ngrp) {
+      const int32_t qb = rp[j] - p0, qe = rp[j + 1] - p0;
       VT acc = 0;
       for (int32_t q = qb + lane; q < qe; q += gsz) acc += vals[q];
       for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, gsz);
-      if (lane == 0) {
-        VT y = sig * acc * invdeg[r];
-        if (has_prev) y -= pc * Y[r];
-        Y[r] = y;
-        apart += deg[r] * (double)y * ((double)sig * (double)Ucur[r]);
-      }
+      if (lane == 0) rsum[j] = acc;
+    }
+    __syncthreads();
+    for (int32_t j = tid; j < nrows; j += SPMV_THREADS) {
+      const int32_t r = r0 + j;
+      VT y = sig * rsum[j] * invdeg[r];
+      if (has_prev) y -= pc * Y[r];
+      Y[r] = y;
+      apart += deg[r] * (double)y * ((double)sig * (double)Ucur[r]);
     }
   }
   apart = block_sum(apart, red);

@@ -1,0 +1,140 @@
+"""GPU parity of the batched Lanczos path (rd_query_batch) against the CPU
+FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+from oracle import dense as D
+from oracle import lanczos as LZ
+from paper_2601_11159_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2601_11159_amd import rd  # noqa: E402
+
+
+def _opts(**kw):
+    return rd.rd_default_options(**kw)
+
+
+@pytest.mark.parametrize("width", [16, 32, 64, 128, 256])
+def test_grid64_batch_fp64_all_widths(width):
+    g = I.grid(64, 64)
+    s, t = I.uniform_pairs(g.n, 100, seed=1)
+    truth = D.rd_all(g, s, t)
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, 1e-8, _opts(block_width=width))
+    assert np.all(out["status"] == rd.RD_OK)
+    err = np.abs(out["r"] - truth) / truth
+    print(f"width {width}: max rel err {err.max():.3e} iters {out['iters'].min()}..{out['iters'].max()}")
+    assert err.max() <= 1e-6
+    assert np.mean(err <= 1e-8) >= 0.95
+    # same stopping decisions as the single-pair path up to rounding
+    for p in range(0, 100, 17):
+        single = G.query(int(s[p]), int(t[p]), 1e-8)
+        assert abs(int(single.iters) - int(out["iters"][p])) <= 1
+        assert out["r"][p] == pytest.approx(single.r, rel=1e-9)
+
+
+def test_batch_matches_literal_algorithm_fixed_k():
+    g = I.road_like(60, seed=9)
+    s, t = I.uniform_pairs(g.n, 40, seed=3)
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, 0.0, _opts(block_width=32, fixed_k=25))
+    A, d = LZ.normalized_adjacency(g)
+    for p in range(len(s)):
+        run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), k=25, A=A, d=d)
+        assert out["iters"][p] == 25
+        assert out["r"][p] == pytest.approx(run.r, rel=1e-10)
+
+
+def test_refill_with_uneven_pairs_and_degenerate_entries():
+    # 300 pairs through 32 slots: pairs differ in length (near and far pairs
+    # on a grid), some pairs repeat a node (r = 0), all must come back.
+    g = I.grid(40, 40)
+    s, t = I.uniform_pairs(g.n, 300, seed=4)
+    t[::7] = s[::7] + 1  # neighbours: short runs
+    t[5::50] = s[5::50]  # s == t
+    truth = np.where(s == t, 0.0, 0.0)
+    mask = s != t
+    truth[mask] = D.rd_all(g, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, 1e-9, _opts(block_width=32))
+    assert np.all(out["status"] == rd.RD_OK)
+    assert np.all(out["r"][~mask] == 0.0) and np.all(out["iters"][~mask] == 0)
+    err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+    assert err.max() <= 1e-7
+    assert out["iters"][mask].min() < out["iters"][mask].max()
+
+
+def test_weighted_batch():
+    g = I.random_connected(600, extra=4000, seed=8, weighted=True)
+    Lp = D.pinv(D.laplacian(g))
+    s, t = I.uniform_pairs(g.n, 70, seed=6)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    for prec, tol, bar in [(rd.RD_F64, 1e-10, 1e-8), (rd.RD_F32, 1e-6, 1e-4)]:
+        out = G.query_batch(s, t, tol, _opts(block_width=64, precision=prec))
+        err = np.abs(out["r"] - D.rd_from_pinv(Lp, s, t)) / D.rd_from_pinv(Lp, s, t)
+        assert err.max() <= bar, (prec, err.max())
+
+
+def test_chung_lu_fp32_batch_with_long_rows():
+    # power-law graph with rows longer than the short-row limit (1024)
+    g = I.chung_lu(300000, 2.1, 20, seed=2)
+    assert g.degrees().max() > 2048
+    A, d = LZ.normalized_adjacency(g)
+    s, t = I.uniform_pairs(g.n, 200, seed=7)
+    hs, ht = I.hub_pairs(g, 56, seed=8)
+    s = np.concatenate([s, hs])
+    t = np.concatenate([t, ht])
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, 1e-4, _opts(precision=rd.RD_F32))
+    assert np.all(out["status"] == rd.RD_OK)
+    idx = list(range(0, len(s), 16)) + list(range(200, 256, 8))
+    for p in idx:
+        run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-10, A=A, d=d)
+        assert abs(out["r"][p] - run.r) / run.r <= 1e-4
+    out64 = G.query_batch(s[:64], t[:64], 1e-8, _opts(precision=rd.RD_F64, block_width=64))
+    for p in range(0, 64, 9):
+        run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-8, A=A, d=d)
+        assert out64["r"][p] == pytest.approx(run.r, rel=1e-9)
+
+
+def test_device_pointer_batch():
+    g = I.grid(32, 32)
+    s, t = I.uniform_pairs(g.n, 50, seed=9)
+    truth = D.rd_all(g, s, t)
+    G = rd.RDGraph(g.n, torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda())
+    ds = torch.from_numpy(s).cuda()
+    dt = torch.from_numpy(t).cuda()
+    out = torch.zeros(50 * 24, dtype=torch.uint8, device="cuda")
+    opts = _opts(block_width=32, stream=torch.cuda.current_stream().cuda_stream)
+    G.query_batch(ds, dt, 1e-10, opts, out=out)
+    res = np.frombuffer(out.cpu().numpy().tobytes(), dtype=rd.RESULT_DTYPE)
+    assert np.max(np.abs(res["r"] - truth) / truth) <= 1e-8
+
+
+def test_batch_argument_errors():
+    g = I.grid(8, 8)
+    G = rd.RDGraph(g.n, g.u, g.v)
+    with pytest.raises(rd.RdError) as e:
+        G.query_batch(np.array([0, 1], np.int32), np.array([5, 64], np.int32), 1e-6)
+    assert e.value.code == rd.RD_E_ARG
+    with pytest.raises(rd.RdError):
+        G.query_batch(np.array([0], np.int32), np.array([5], np.int32), 1e-6, _opts(block_width=48))
+    assert len(G.query_batch(np.zeros(0, np.int32), np.zeros(0, np.int32), 1e-6)) == 0
+
+
+def test_autotuned_width_runs():
+    g = I.chung_lu(50000, 2.3, 32, seed=4)
+    s, t = I.uniform_pairs(g.n, 300, seed=2)
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, 1e-4, _opts(precision=rd.RD_F32))
+    A, d = LZ.normalized_adjacency(g)
+    for p in range(0, 300, 50):
+        run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-10, A=A, d=d)
+        assert abs(out["r"][p] - run.r) / run.r <= 1e-4
