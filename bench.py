@@ -1,0 +1,234 @@
+"""Benchmark: resistance-distance queries per second on one MI355X.
+
+Workload (default): batched queries on a Chung-Lu power-law graph with
+n = 4,000,000, degree exponent 2.3, mean degree 32 (about 64M undirected
+edges, unit weights, largest connected component), 4,096 (s,t) pairs - half
+uniform, half with s among the top 1% nodes by degree - each run to a relative
+tolerance of 1e-4 with FP32 sparse products and FP64 Lanczos scalars.
+
+One step = one rd_query_batch call over all pairs, with the graph, the pair
+lists and the result array resident in device memory. Printed beside it:
+  * the plain single-pair FP64 loop (rd_query) on the same GPU and graph, on
+    a sample of the same pairs, and the batched/plain ratio;
+  * the roofline of the dominant kernel (the batched short-row sparse
+    product), its live duration from HIP events recorded around each launch;
+  * the CPU FP64 oracle timed on a bounded sample of pairs;
+  * the relative error of the timed GPU results against that oracle sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RD queries/s at 1e-4 rel err (batched FP32 vs plain FP64) + SpMV HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+EPS = 1e-4
+
+WORKLOADS = {
+    "chung_lu_n4M_g2.3_d32_4096pairs": dict(n=4_000_000, gamma=2.3, mean_deg=32.0, seed=4,
+                                             pairs=4096, pair_seed=4, hub_seed=40),
+    # smaller stand-in for quick checks
+    "chung_lu_n500k_g2.3_d32_1024pairs": dict(n=500_000, gamma=2.3, mean_deg=32.0, seed=4,
+                                               pairs=1024, pair_seed=4, hub_seed=40),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2601_11159_amd", "csrc", "lanczos_batch.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, width: int):
+    """Measured HBM bytes per launch of k_spmm_short for this workload and
+    width, from the committed counter summary, when the kernel source is
+    unchanged since it was taken."""
+    p = os.path.join(ROOT, "profiles", "spmm_short_traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{workload}/B{width}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(g, s, t, budget_s: float = 20.0):
+    """The CPU FP64 oracle (literal Algorithm 3, numpy/scipy) on a bounded
+    sample of the same pairs, single thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import lanczos as LZ
+
+    t0 = time.time()
+    A, d = LZ.normalized_adjacency(g)
+    setup = time.time() - t0
+    vals, times = [], []
+    with threadpool_limits(limits=1):
+        for p in range(len(s)):
+            t1 = time.time()
+            run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=EPS, A=A, d=d)
+            times.append(time.time() - t1)
+            vals.append(run.r)
+            if sum(times) > budget_s:
+                break
+    return np.array(vals), float(sum(times)), setup
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chung_lu_n4M_g2.3_d32_4096pairs", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--plain-pairs", type=int, default=128)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(pairs would shard across GPUs with no per-step communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    from paper_2601_11159_amd import inputs as I
+    from paper_2601_11159_amd import rd
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.time()
+    g = I.chung_lu(wl["n"], wl["gamma"], wl["mean_deg"], wl["seed"])
+    half = wl["pairs"] // 2
+    s1, t1 = I.uniform_pairs(g.n, half, wl["pair_seed"])
+    s2, t2 = I.hub_pairs(g, wl["pairs"] - half, wl["hub_seed"])
+    s = np.concatenate([s1, s2]).astype(np.int32)
+    t = np.concatenate([t1, t2]).astype(np.int32)
+    log(f"graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
+
+    t0 = time.time()
+    G = rd.RDGraph(g.n, torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda())
+    torch.cuda.synchronize()
+    log(f"rd_init_graph {time.time() - t0:.2f}s")
+    ds = torch.from_numpy(s).cuda()
+    dt = torch.from_numpy(t).cuda()
+    dout = torch.zeros(len(s) * 24, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    # autotune the width once (kept on the handle), then warm up
+    t0 = time.time()
+    width = G.tune_width(rd.RD_F32, len(s), stream)
+    opts_prof = rd.rd_default_options(precision=rd.RD_F32, stream=stream, flags=rd.RD_PROFILE,
+                                      block_width=width)
+    for _ in range(args.warmup):
+        G.query_batch(ds, dt, EPS, opts_prof, out=dout)
+    torch.cuda.synchronize()
+    G.kernel_stats(0)  # reset counters
+    log(f"autotune (width {width}) + warmup {time.time() - t0:.1f}s")
+
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        G.query_batch(ds, dt, EPS, opts_prof, out=dout)
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    k_ms, k_launches, k_bytes = G.kernel_stats(0)
+    res = np.frombuffer(dout.cpu().numpy().tobytes(), dtype=rd.RESULT_DTYPE).copy()
+    value = len(s) * args.steps / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+    iters = res["iters"]
+    log(f"batched: {value:.1f} q/s, {ms_per_step:.1f} ms/step, iters mean {iters.mean():.2f} "
+        f"max {iters.max()}, statuses {np.unique(res['status'])}")
+
+    # plain single-pair FP64 loop on a sample of the same pairs (half uniform, half hub)
+    npl = min(args.plain_pairs, len(s))
+    idx = np.concatenate([np.arange(npl // 2), half + np.arange(npl - npl // 2)])
+    popts = rd.rd_default_options(precision=rd.RD_F64, flags=rd.RD_PROFILE)
+    G.query(int(s[0]), int(t[0]), EPS, popts)
+    G.kernel_stats(1)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plain_r = np.zeros(npl)
+    plain_it = np.zeros(npl, dtype=np.int64)
+    for j, p in enumerate(idx):
+        rr = G.query(int(s[p]), int(t[p]), EPS, popts)
+        plain_r[j] = rr.r
+        plain_it[j] = rr.iters
+    torch.cuda.synchronize()
+    plain_elapsed = time.time() - t0
+    plain_value = npl / plain_elapsed
+    pk_ms, pk_launches, pk_bytes = G.kernel_stats(1)
+    log(f"plain fp64: {plain_value:.1f} q/s, iters mean {plain_it.mean():.2f}")
+
+    # roofline of the dominant kernel
+    avg_ms = k_ms / max(k_launches, 1)
+    achieved = k_bytes / (avg_ms * 1e-3) / 1e9 if k_launches else None
+    traffic = load_traffic(args.workload, width) if width else None
+    roofline = {
+        "kernel": "k_spmm_short (batched FP32 sparse product, rows of length <= 1024)",
+        "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": k_launches,
+        "alg_bytes_per_launch": k_bytes,
+    }
+    plain_avg_ms = pk_ms / max(pk_launches, 1)
+    plain_roof = {
+        "kernel": "k_spmv (single-pair FP64 sparse product)",
+        "achieved": round(pk_bytes / (plain_avg_ms * 1e-3) / 1e9, 1) if pk_launches else None,
+        "avg_launch_ms": round(plain_avg_ms, 4), "launches": pk_launches,
+    }
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        sample = np.array([0, 1, half, half + 1])
+        vals, secs, setup = cpu_baseline(g, s[sample], t[sample])
+        done = len(vals)
+        cpu = {"value": round(done / secs, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} of the {len(s)} pairs (2 uniform, 2 hub-source), literal "
+                         f"Algorithm 3 in numpy/scipy FP64 at the same 1e-4 tolerance, "
+                         f"{secs:.1f}s after a {setup:.1f}s operator build"}
+        gpu_b = res["r"][sample[:done]]
+        gpu_p = plain_r[[0, 1, npl // 2, npl // 2 + 1][:done]] if npl >= 4 else None
+        parity = {"pairs": int(done),
+                  "batched_fp32_max_rel_err_vs_oracle": float(np.max(np.abs(gpu_b - vals) / vals)),
+                  "plain_fp64_max_rel_err_vs_oracle":
+                      float(np.max(np.abs(gpu_p - vals) / vals)) if gpu_p is not None else None}
+        log(f"cpu oracle: {cpu['value']} q/s; parity {parity}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "pairs": len(s), "eps_rel": EPS,
+                   "precision": "FP32 vectors and sparse products, FP64 Lanczos scalars",
+                   "block_width": width, "block_width_source": "autotuned", "mean_iters": round(float(iters.mean()), 3)},
+        "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,
+                       "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof},
+        "speedup_batched_vs_plain_fp64": round(value / plain_value, 2),
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,6 +53,7 @@ typedef enum {
 
 /* flags */
 #define RD_DEVICE_PTRS 0x1u
+#define RD_PROFILE 0x2u /* rd_options.flags: time the sparse-product launches (see rd_kernel_stats) */
 
 /* weight / vector dtypes */
 #define RD_F64 0
@@ -137,6 +138,16 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
                          double eps, const rd_options *o, rd_result *out);
 
 /*
+ * The block width rd_query_batch uses when rd_options.block_width is 0: the
+ * width among 32, 64, 128, 256 (not wider than needed for npairs) whose
+ * sparse product takes the least time per column on this graph, measured on
+ * first use with HIP events on `stream` (NULL: the handle's stream) and kept
+ * on the handle; with the environment variable RD_AUTOTUNE_CACHE naming a
+ * file, choices are also read from and appended to that file.
+ */
+rd_status rd_tune_width(rd_graph g, int32_t precision, int32_t npairs, void *stream, int32_t *width);
+
+/*
  * Edge-weight gradient of L = sum_p grad_r[p] r(s_p, t_p):
  *   grad_w[e] = -sum_p grad_r[p] (phi_p(u_e) - phi_p(v_e))^2,
  * with phi_p = L^+ (e_s - e_t) estimated as in line 1 of Algorithm 5 from the
@@ -148,6 +159,20 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
 rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
                         const double *grad_r, double eps, const rd_options *o, rd_result *fwd,
                         float *grad_w);
+
+/*
+ * Diagnostic: timing of the sparse-product launches recorded by calls made
+ * with RD_PROFILE in rd_options.flags, since the previous rd_kernel_stats call
+ * (which resets the counters). which = 0: the batched product over rows of
+ * length <= 1024 (k_spmm_short); which = 1: the single-pair product (k_spmv).
+ * Durations come from HIP events recorded around each launch on the stream it
+ * runs on. alg_bytes receives the algorithmic bytes of one launch of the last
+ * recorded configuration: adjacency indices (and values, if weighted) of the
+ * rows it covers, row offsets, the gathered vector block read once, the
+ * previous block read and the result block written, and the degree arrays.
+ */
+rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *launches,
+                          double *alg_bytes);
 
 /* Release the handle and its device memory. NULL is ignored. */
 void rd_free_graph(rd_graph g);

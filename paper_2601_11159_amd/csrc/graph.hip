@@ -270,7 +270,41 @@ rd_options resolve_options(rd_graph g, const rd_options *o) {
   return r;
 }
 
+std::pair<hipEvent_t, hipEvent_t> KernelTimer::next() {
+  if (used == pool.size()) {
+    hipEvent_t a, b;
+    RD_HIP(hipEventCreate(&a));
+    RD_HIP(hipEventCreate(&b));
+    pool.push_back({a, b});
+  }
+  return pool[used++];
+}
+
+void KernelTimer::resolve(size_t valid) {
+  for (size_t i = 0; i < used && i < valid; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pool[i].first, pool[i].second) == hipSuccess) {
+      total_ms += ms;
+      ++launches;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  used = 0;
+}
+
+void KernelTimer::release() {
+  for (auto &p : pool) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  pool.clear();
+  used = 0;
+}
+
 static void free_graph_memory(rd_graph g) {
+  g->timer[0].release();
+  g->timer[1].release();
   plain_free(g);
   batch_free(g);
   dev_free(g->row_ptr);
@@ -322,6 +356,18 @@ const char *rd_status_string(rd_status s) {
 static thread_local std::string g_init_error;
 
 const char *rd_last_error(rd_graph g) { return g ? g->err.c_str() : g_init_error.c_str(); }
+
+rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *launches,
+                          double *alg_bytes) {
+  if (!g || which < 0 || which > 1) return RD_E_ARG;
+  KernelTimer &k = g->timer[which];
+  if (total_ms) *total_ms = k.total_ms;
+  if (launches) *launches = k.launches;
+  if (alg_bytes) *alg_bytes = k.alg_bytes;
+  k.total_ms = 0;
+  k.launches = 0;
+  return RD_OK;
+}
 
 rd_status rd_graph_info(rd_graph g, int32_t *n, int64_t *m, int64_t *nnz) {
   if (!g) return RD_E_ARG;

@@ -102,7 +102,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
     int32_t nwi, const int32_t *__restrict__ witem_row, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
     const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
-    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp) {
+    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp,
+    const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   using V = VecN<VT, VEC>;
@@ -175,7 +177,9 @@ __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
     const int32_t *__restrict__ long_rows, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
     const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
-    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp, int32_t poff) {
+    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp, int32_t poff,
+    const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   constexpr int NG = (LONG_THREADS / 64) * S::RPW;  // sub-rows per block
@@ -245,7 +249,9 @@ __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
 
 // out[j] = sum_k part[j * ldp + k], k < np (block j, fixed order).
 __global__ __launch_bounds__(COL_THREADS) void k_col_sum(const double *__restrict__ part, int32_t ldp,
-                                                         int32_t np, double *__restrict__ out) {
+                                                         int32_t np, double *__restrict__ out,
+                                                         const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   __shared__ double sm[COL_THREADS / 64];
   const double *p = part + (size_t)blockIdx.x * ldp;
   double a = 0.0;
@@ -280,6 +286,9 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
                                                  const double *__restrict__ deg,
                                                  rd_result *__restrict__ out,
                                                  int32_t *__restrict__ qstate) {
+  // qstate: [0] next pair, [1] active columns, [2] iterations with work, [3] constant 1.
+  // Every call but the first (which fills the slots) returns once no column is active.
+  if (qstate[1] == 0 && qstate[2] > 0) return;
   __shared__ int32_t need[256];
   __shared__ int32_t newpair[256];
   const int j = threadIdx.x;
@@ -350,7 +359,11 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
   for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
   if ((j & 63) == 0) cnt[j >> 6] = a;
   __syncthreads();
-  if (j == 0) qstate[1] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+  if (j == 0) {
+    const int32_t total = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    qstate[1] = total;
+    if (total > 0) qstate[2] += 1;  // the next sparse product does work
+  }
 }
 
 // W = Y - alpha sig U_cur for running columns (in place over Y), the start
@@ -360,7 +373,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
                                                           const VT *__restrict__ Ucur,
                                                           VT *__restrict__ Y,
                                                           const ColCtrl *__restrict__ ctrl,
-                                                          double *__restrict__ part, int32_t ldp) {
+                                                          double *__restrict__ part, int32_t ldp,
+                                                          const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   using V = VecN<VT, VEC>;
@@ -409,7 +424,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
 // beta_{i+1} of every running column and the next scales.
 __global__ __launch_bounds__(COL_THREADS) void k_beta(const double *__restrict__ part, int32_t ldp,
                                                       int32_t np, LzState *__restrict__ st,
-                                                      ColCtrl *__restrict__ ctrl) {
+                                                      ColCtrl *__restrict__ ctrl,
+                                                      const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   __shared__ double sm[COL_THREADS / 64];
   const int j = blockIdx.x;
   const double *p = part + (size_t)j * ldp;
@@ -452,6 +469,8 @@ __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__re
   if (j == 0) {
     qstate[0] = 0;
     qstate[1] = 0;
+    qstate[2] = 0;
+    qstate[3] = 1;
   }
 }
 
@@ -472,6 +491,8 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 struct BatchWork {
   // schedule (independent of B and precision)
   int32_t nwi = 0, nlong = 0;
+  int64_t nnz_short = 0;  // adjacency entries of rows handled by k_spmm_short
+  int32_t n_short = 0;    // rows handled by k_spmm_short
   int32_t *witem_row = nullptr;  // [nwi+1]
   int32_t *long_rows = nullptr;  // [nlong]
   int32_t grid_short = 0, grid_upd = 0;
@@ -484,7 +505,7 @@ struct BatchWork {
   double *colsum = nullptr;  // [Bcap]
   LzState *st = nullptr;
   ColCtrl *ctrl = nullptr;
-  int32_t *qstate = nullptr;       // [2]: queue head, active columns
+  int32_t *qstate = nullptr;       // [4]: queue head, active columns, working iterations, 1
   int32_t *qstate_host = nullptr;  // pinned
   int32_t *flag = nullptr;
   // autotune cache: chosen width per precision
@@ -535,6 +556,9 @@ static BatchWork *batch_get(rd_graph g) {
   }
   items.push_back(g->n);
   bw->nwi = (int32_t)items.size() - 1;
+  bw->n_short = g->n - (int32_t)longs.size();
+  bw->nnz_short = g->nnz;
+  for (int32_t lr : longs) bw->nnz_short -= rp[lr + 1] - rp[lr];
   bw->nlong = (int32_t)longs.size();
   bw->witem_row = (int32_t *)dev_alloc(items.size() * sizeof(int32_t));
   RD_HIP(hipMemcpy(bw->witem_row, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -552,9 +576,9 @@ static BatchWork *batch_get(rd_graph g) {
   bw->st = (LzState *)dev_alloc(256 * sizeof(LzState));
   bw->ctrl = (ColCtrl *)dev_alloc(256 * sizeof(ColCtrl));
   bw->colsum = (double *)dev_alloc(256 * sizeof(double));
-  bw->qstate = (int32_t *)dev_alloc(2 * sizeof(int32_t));
+  bw->qstate = (int32_t *)dev_alloc(4 * sizeof(int32_t));
   bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
-  RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 2 * sizeof(int32_t), hipHostMallocDefault));
+  RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 4 * sizeof(int32_t), hipHostMallocDefault));
   return bw;
 }
 
@@ -578,7 +602,8 @@ static void batch_reserve(rd_graph g, BatchWork *bw, int32_t B, size_t elem) {
 }
 
 template <typename VT, int B, bool WEIGHTED>
-static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStream_t st) {
+static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStream_t st,
+                        const int32_t *active, bool prof = false) {
   const VT *w = nullptr;
   const VT *invdeg;
   if constexpr (sizeof(VT) == 8) {
@@ -588,39 +613,53 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
     w = (const VT *)g->w32;
     invdeg = (const VT *)g->invdeg32;
   }
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  if (prof) {
+    ev = g->timer[0].next();
+    RD_HIP(hipEventRecord(ev.first, st));
+  }
   hipLaunchKernelGGL((k_spmm_short<VT, B, WEIGHTED>), dim3(bw->grid_short), dim3(SHORT_THREADS), 0, st,
                      bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
-                     bw->part, bw->ldp);
+                     bw->part, bw->ldp, active);
+  if (prof) {
+    RD_HIP(hipEventRecord(ev.second, st));
+    const double sv = sizeof(VT);
+    g->timer[0].alg_bytes = (double)bw->nnz_short * (4.0 + (WEIGHTED ? sv : 0.0)) +
+                            4.0 * ((double)bw->n_short + bw->nwi + 1) +
+                            sv * B * ((double)g->n + 2.0 * bw->n_short) +
+                            (sv + 8.0) * (double)bw->n_short;
+  }
   if (bw->nlong > 0)
     hipLaunchKernelGGL((k_spmm_long<VT, B, WEIGHTED>), dim3(bw->nlong), dim3(LONG_THREADS), 0, st,
                        bw->long_rows, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
-                       bw->part, bw->ldp, bw->grid_short);
+                       bw->part, bw->ldp, bw->grid_short, active);
 }
 
 template <typename VT, int B>
 static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const RunParams &prm,
                                     const int32_t *ps, const int32_t *pt, rd_result *out,
-                                    hipStream_t st) {
+                                    hipStream_t st, bool prof) {
   const VT *Ucur = (const VT *)bw->X[cur];
   VT *Y = (VT *)bw->X[1 - cur];
   if (g->unit)
-    launch_spmm<VT, B, false>(g, bw, Ucur, Y, st);
+    launch_spmm<VT, B, false>(g, bw, Ucur, Y, st, bw->qstate + 1, prof);
   else
-    launch_spmm<VT, B, true>(g, bw, Ucur, Y, st);
+    launch_spmm<VT, B, true>(g, bw, Ucur, Y, st, bw->qstate + 1, prof);
   hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
-                     bw->grid_short + bw->nlong, bw->colsum);
+                     bw->grid_short + bw->nlong, bw->colsum, bw->qstate + 1);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     Ucur, Y, bw->ctrl, bw->part, bw->ldp);
+                     Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1);
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
-                     bw->st, bw->ctrl);
+                     bw->st, bw->ctrl, bw->qstate + 1);
 }
 
 // Run all pairs through B slots. Returns the number of iterations enqueued.
 template <typename VT, int B>
 static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
-                           const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st) {
+                           const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
+                           bool prof) {
   batch_reserve(g, bw, B, sizeof(VT));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   // fill the slots: control with every column idle pops the first B pairs,
@@ -628,7 +667,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp);
+                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp, bw->qstate + 1);
   RD_HIP(hipGetLastError());
   int cur = 0;
   int64_t iters = 0;
@@ -636,29 +675,32 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   const int64_t cap = (int64_t)prm.max_iters * ((npairs + B - 1) / B + 1) + 16;
   for (;;) {
     for (int j = 0; j < chunk; ++j) {
-      enqueue_batch_iteration<VT, B>(g, bw, cur, prm, ps, pt, out, st);
+      enqueue_batch_iteration<VT, B>(g, bw, cur, prm, ps, pt, out, st, prof);
       cur ^= 1;
     }
     iters += chunk;
     RD_HIP(hipGetLastError());
-    RD_HIP(hipMemcpyAsync(bw->qstate_host, bw->qstate, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipMemcpyAsync(bw->qstate_host, bw->qstate, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RD_HIP(hipStreamSynchronize(st));
     if (bw->qstate_host[1] == 0) break;
     RD_REQUIRE(iters < cap, "batched run did not drain (internal error)");
     chunk = std::min(chunk * 2, 64);
   }
+  // sparse products enqueued after the last active iteration returned at once
+  if (prof) g->timer[0].resolve((size_t)bw->qstate_host[2]);
   return iters;
 }
 
 template <typename VT>
 static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
-                              const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st) {
+                              const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
+                              bool prof) {
   switch (B) {
-    case 16: return batch_run_t<VT, 16>(g, bw, npairs, ps, pt, prm, out, st);
-    case 32: return batch_run_t<VT, 32>(g, bw, npairs, ps, pt, prm, out, st);
-    case 64: return batch_run_t<VT, 64>(g, bw, npairs, ps, pt, prm, out, st);
-    case 128: return batch_run_t<VT, 128>(g, bw, npairs, ps, pt, prm, out, st);
-    case 256: return batch_run_t<VT, 256>(g, bw, npairs, ps, pt, prm, out, st);
+    case 16: return batch_run_t<VT, 16>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    case 32: return batch_run_t<VT, 32>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    case 64: return batch_run_t<VT, 64>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    case 128: return batch_run_t<VT, 128>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    case 256: return batch_run_t<VT, 256>(g, bw, npairs, ps, pt, prm, out, st, prof);
   }
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
@@ -669,13 +711,13 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   batch_reserve(g, bw, B, sizeof(VT));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp);
+                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp, bw->qstate + 3);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
   auto once = [&]() {
-    if (g->unit) launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st);
-    else launch_spmm<VT, B, true>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st);
+    if (g->unit) launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st, bw->qstate + 3);
+    else launch_spmm<VT, B, true>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st, bw->qstate + 3);
   };
   once();
   RD_HIP(hipEventRecord(e0, st));
@@ -784,10 +826,11 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
     RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
+    const bool prof = opt.flags & RD_PROFILE;
     if (opt.precision == RD_F64)
-      batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st);
+      batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
     else
-      batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st);
+      batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
     if (!dp) {
       RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
     }
@@ -809,3 +852,18 @@ rd_status rd_grad_edges(rd_graph g, int32_t, const int32_t *, const int32_t *, c
 }
 
 }  // extern "C"
+
+extern "C" rd_status rd_tune_width(rd_graph g, int32_t precision, int32_t npairs, void *stream,
+                                   int32_t *width) {
+  if (!g || !width || npairs < 1 || (precision != RD_F64 && precision != RD_F32)) return RD_E_ARG;
+  try {
+    g->err.clear();
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = stream ? (hipStream_t)stream : g->own_stream;
+    *width = autotune_width(g, batch_get(g), precision, npairs, st);
+    return RD_OK;
+  } catch (const RdError &e) {
+    g->err = e.msg;
+    return e.code;
+  }
+}

@@ -244,9 +244,14 @@ static PlainWork *plain_get(rd_graph g) {
 
 template <typename VT>
 static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st, double *tr_alpha,
-                              double *tr_beta, double *tr_rhat) {
+                              double *tr_beta, double *tr_rhat, bool prof) {
   const VT *Ucur = (const VT *)pw->U[cur];
   VT *Y = (VT *)pw->U[1 - cur];
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  if (prof) {
+    ev = g->timer[1].next();
+    RD_HIP(hipEventRecord(ev.first, st));
+  }
   if (g->unit)
     hipLaunchKernelGGL((k_spmv<VT, false>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
                        g->blk_lanes, g->row_ptr, g->col, (const VT *)nullptr,
@@ -255,6 +260,12 @@ static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st
     hipLaunchKernelGGL((k_spmv<VT, true>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
                        g->blk_lanes, g->row_ptr, g->col, VecTraits<VT>::w(g),
                        VecTraits<VT>::invdeg(g), g->deg, Ucur, Y, pw->part, pw->st);
+  if (prof) {
+    RD_HIP(hipEventRecord(ev.second, st));
+    const double sv = sizeof(VT);
+    g->timer[1].alg_bytes = (double)g->nnz * (4.0 + (g->unit ? 0.0 : sv)) + 4.0 * (g->n + 1) +
+                            3.0 * sv * g->n + (sv + 8.0) * g->n;
+  }
   hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(RED_THREADS), 0, st, pw->part, g->nblk, pw->st,
                      tr_alpha, tr_rhat);
   hipLaunchKernelGGL(k_update<VT>, dim3(pw->upd_blocks), dim3(UPD_THREADS), 0, st, g->n, g->deg,
@@ -277,7 +288,7 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
   for (;;) {
     const int todo = std::min(chunk, cap - done_iters);
     for (int j = 0; j < todo; ++j) {
-      enqueue_iteration<VT>(g, pw, cur, st, tr_alpha, tr_beta, tr_rhat);
+      enqueue_iteration<VT>(g, pw, cur, st, tr_alpha, tr_beta, tr_rhat, o.flags & RD_PROFILE);
       cur ^= 1;
     }
     RD_HIP(hipGetLastError());
@@ -288,6 +299,8 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
     chunk = std::min(2 * chunk, 256);
   }
   const LzState &S = *pw->st_host;
+  // launches after the stopping iteration returned at once: count the first k
+  if (o.flags & RD_PROFILE) g->timer[1].resolve((size_t)S.k);
   int32_t status = S.status;
   if (status == LZ_RUNNING) status = LZ_NOT_CONVERGED;  // cap reached while still running
   out->r = S.rhat;

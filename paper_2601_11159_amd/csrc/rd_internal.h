@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "rd.h"
 
@@ -69,6 +71,18 @@ struct LzState {
 struct PlainWork;
 struct BatchWork;
 
+// Event-timed launches of one kernel (RD_PROFILE).
+struct KernelTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  size_t used = 0;       // events recorded in the current call
+  double total_ms = 0;   // resolved durations since the last read
+  int64_t launches = 0;
+  double alg_bytes = 0;  // algorithmic bytes of one launch (last configuration)
+  std::pair<hipEvent_t, hipEvent_t> next();
+  void resolve(size_t valid);  // after the stream is synchronised: count the first `valid` launches
+  void release();
+};
+
 struct rd_graph_s {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -92,6 +106,7 @@ struct rd_graph_s {
   int32_t *blk_row = nullptr;  // [nblk+1] first row of each block
   int8_t *blk_lanes = nullptr; // [nblk] log2(lanes per row) for multi-row blocks, -1 for one long row
 
+  KernelTimer timer[2];  // 0: batched short-row product, 1: single-pair product
   PlainWork *plain = nullptr;
   BatchWork *batch = nullptr;
 

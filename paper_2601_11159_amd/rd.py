@@ -27,13 +27,14 @@ RD_E_NOT_CONVERGED = 5
 RD_E_BREAKDOWN = 6
 
 RD_DEVICE_PTRS = 0x1
+RD_PROFILE = 0x2
 RD_F64 = 0
 RD_F32 = 1
 
 EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
-    "rd_last_error",
+    "rd_last_error", "rd_kernel_stats", "rd_tune_width",
 ]
 
 
@@ -94,6 +95,10 @@ def load(path: str = LIB_PATH):
     for f in (lib.rd_init_graph, lib.rd_set_weights, lib.rd_graph_info, lib.rd_query,
               lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges):
         f.restype = ctypes.c_int
+    lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
+    lib.rd_tune_width.restype = ctypes.c_int
+    lib.rd_kernel_stats.argtypes = [vp, i32, P(dbl), P(i64), P(dbl)]
+    lib.rd_kernel_stats.restype = ctypes.c_int
     lib.rd_free_graph.argtypes = [vp]
     lib.rd_free_graph.restype = None
     lib.rd_status_string.argtypes = [ctypes.c_int]
@@ -208,6 +213,23 @@ class RDGraph:
         if rc != RD_OK:
             self._raise(rc, "rd_graph_info")
         return n.value, m.value, nnz.value
+
+    def tune_width(self, precision: int, npairs: int, stream=None) -> int:
+        w = ctypes.c_int32()
+        rc = load().rd_tune_width(self._h, int(precision), int(npairs), stream, ctypes.byref(w))
+        if rc != RD_OK:
+            self._raise(rc, "rd_tune_width")
+        return w.value
+
+    def kernel_stats(self, which: int):
+        """(total ms, launches, algorithmic bytes per launch) of the sparse
+        product launches timed under RD_PROFILE since the last call.
+        which = 0: batched short-row product; 1: single-pair product."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        rc = load().rd_kernel_stats(self._h, int(which), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+        if rc != RD_OK:
+            self._raise(rc, "rd_kernel_stats")
+        return ms.value, n.value, b.value
 
     def set_weights(self, w):
         is32 = str(getattr(w, "dtype", "")).endswith("float32")
