@@ -38,7 +38,9 @@ constexpr int LONG_DEG = 1024;   // rows longer than this go to the split-row ke
 constexpr int WAVE_NNZ = 256;    // adjacency entries per wave work item (short rows)
 constexpr int COL_THREADS = 256;
 
-enum : int32_t { COL_RUN = 0, COL_REFILL = 1, COL_IDLE = 2 };
+// COL_FINAL: the run stopped at this iteration; only the potential is updated
+// (gradient mode), then the column is idle.
+enum : int32_t { COL_RUN = 0, COL_REFILL = 1, COL_IDLE = 2, COL_FINAL = 3 };
 
 struct ColCtrl {
   double sig;   // q = sig * U_cur[:, j]
@@ -46,6 +48,8 @@ struct ColCtrl {
   double coef;  // alpha * sig for the update
   double vs;    // start vector entries of a refilled column at rows s and t
   double vt;
+  double pa;    // gradient mode: p_i = q_i + pa p_{i-1}
+  double xb;    //                x_i = x_{i-1} + xb p_i
   int32_t mode;  // COL_*
   int32_t s, t;
   int32_t pad;
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
                                                  const int32_t *__restrict__ pt,
                                                  const double *__restrict__ deg,
                                                  rd_result *__restrict__ out,
-                                                 int32_t *__restrict__ qstate) {
+                                                 int32_t *__restrict__ qstate, int32_t grad) {
   // qstate: [0] next pair, [1] active columns, [2] iterations with work, [3] constant 1.
   // Every call but the first (which fills the slots) returns once no column is active.
   if (qstate[1] == 0 && qstate[2] > 0) return;
@@ -293,9 +297,23 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
   __shared__ int32_t newpair[256];
   const int j = threadIdx.x;
   LzState S;
+  double pa = 0.0, xb = 0.0;
+  bool advanced = false;
   if (j < B) {
     S = st[j];
-    if (S.status == LZ_RUNNING) scalar_after_alpha(S, alpha[j], nullptr, nullptr);
+    const bool was_running = S.status == LZ_RUNNING;
+    const double delta_prev = S.delta, beta_i = S.beta;
+    const int32_t k_prev = S.k;
+    if (was_running) scalar_after_alpha(S, alpha[j], nullptr, nullptr);
+    // coefficients of the potential recurrence for iteration i = S.k: with
+    // I - T_i = L D L^T (unit lower bidiagonal L, subdiagonal -beta_i/delta_{i-1}),
+    // x_i = Q_i (I - T_i)^{-1} e_1 = x_{i-1} + (omega_i/delta_i) p_i and
+    // p_i = q_i + (beta_i/delta_{i-1}) p_{i-1}
+    advanced = was_running && S.k == k_prev + 1;
+    if (advanced) {
+      pa = S.k > 1 ? beta_i / delta_prev : 0.0;
+      xb = S.omega / S.delta;
+    }
     const bool fin = S.status == LZ_DONE || S.status == LZ_NOT_CONVERGED || S.status == LZ_BREAKDOWN;
     if (fin) write_result(out, S);
     need[j] = (fin || S.status == LZ_IDLE) ? 1 : 0;
@@ -340,14 +358,22 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       cc.t = t;
       active = 1;
     } else if (np == -1) {
+      // a run that stopped at this iteration still adds its last term to the
+      // potential (gradient mode); the column is idle afterwards
+      const bool final_term = grad && advanced && S.status != LZ_BREAKDOWN;
       S.status = LZ_IDLE;
-      cc.mode = COL_IDLE;
-      cc.sig = 0.0;
+      cc.mode = final_term ? COL_FINAL : COL_IDLE;
+      cc.pa = pa;
+      cc.xb = xb;
+      if (final_term) active = 1;
       cc.pc = 0.0;
       cc.coef = 0.0;
+      if (!final_term) cc.sig = 0.0;
     } else {
       cc.mode = COL_RUN;
       cc.coef = S.alpha * S.sig_cur;
+      cc.pa = pa;
+      cc.xb = xb;
       active = 1;
     }
     st[j] = S;
@@ -368,13 +394,16 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
 
 // W = Y - alpha sig U_cur for running columns (in place over Y), the start
 // vector for refilled columns, zero for idle ones; per-block sum d W^2.
-template <typename VT, int B>
+// GRAD: also advance the potential of running (and just-stopped) columns,
+// p = sig U_cur + pa p, x = x + xb p (arrays P, X of the same shape).
+template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const double *__restrict__ deg,
                                                           const VT *__restrict__ Ucur,
                                                           VT *__restrict__ Y,
                                                           const ColCtrl *__restrict__ ctrl,
                                                           double *__restrict__ part, int32_t ldp,
-                                                          const int32_t *__restrict__ active) {
+                                                          const int32_t *__restrict__ active,
+                                                          VT *__restrict__ P, VT *__restrict__ X) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -382,8 +411,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
   __shared__ double sm[(SHORT_THREADS / 64) * B];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
-  VT coef[VEC], vs[VEC], vt[VEC];
+  VT coef[VEC], vs[VEC], vt[VEC], sig[VEC], pa[VEC], xb[VEC];
   int32_t mode[VEC], cs[VEC], ct[VEC];
+  bool pot = false;
   double acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
@@ -391,10 +421,14 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     coef[v] = (VT)cc.coef;
     vs[v] = (VT)cc.vs;
     vt[v] = (VT)cc.vt;
+    sig[v] = (VT)cc.sig;
+    pa[v] = (VT)cc.pa;
+    xb[v] = (VT)cc.xb;
     mode[v] = cc.mode;
     cs[v] = cc.s;
     ct[v] = cc.t;
     acc[v] = 0.0;
+    pot = pot || mode[v] == COL_RUN || mode[v] == COL_FINAL;
   }
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
@@ -417,8 +451,79 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
       o.v[v] = x;
     }
     vstore<VT, VEC>(Y + (size_t)r * B + c0, o);
+    if constexpr (GRAD) {
+      if (pot) {
+        V pv = vload<VT, VEC>(P + (size_t)r * B + c0);
+        V xv = vload<VT, VEC>(X + (size_t)r * B + c0);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          if (mode[v] == COL_RUN || mode[v] == COL_FINAL) {
+            const VT p = sig[v] * uc.v[v] + pa[v] * pv.v[v];
+            pv.v[v] = p;
+            xv.v[v] += xb[v] * p;
+          }
+        }
+        vstore<VT, VEC>(P + (size_t)r * B + c0, pv);
+        vstore<VT, VEC>(X + (size_t)r * B + c0, xv);
+      }
+    }
   }
   block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
+}
+
+// Edge gradient for the pairs held in the columns of X (the accumulated
+// potentials in the scaled basis: phi_p = sqrt(c_p) X[:, p]):
+//   gacc[e] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair,
+// for every undirected edge e = (u, v), visited once from its smaller end.
+// One wavefront per row; lanes over columns; FP64 sums.
+template <typename VT, int B>
+__global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
+    int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ eid, const VT *__restrict__ X, const double *__restrict__ cw,
+    double *__restrict__ gacc) {
+  constexpr int VEC = B >= 64 ? B / 64 : 1;
+  using V = VecN<VT, VEC>;
+  const int lane = threadIdx.x & 63;
+  const int c0 = lane * VEC;
+  const bool on = c0 < B;
+  double w[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) w[v] = on ? cw[c0 + v] : 0.0;
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + (threadIdx.x >> 6);
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t u = gw; u < n; u += nwv) {
+    V xu;
+    if (on) xu = vload<VT, VEC>(X + (size_t)u * B + c0);
+    const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
+    for (int32_t p = pb; p < pe; ++p) {
+      const int32_t v = col[p];
+      if (v <= u) continue;  // each edge once, from its smaller end
+      double s = 0.0;
+      if (on) {
+        const V xv = vload<VT, VEC>(X + (size_t)v * B + c0);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          const double d = (double)xu.v[k] - (double)xv.v[k];
+          s += w[k] * d * d;
+        }
+      }
+      s = wave_sum(s);
+      if (lane == 0) gacc[eid[p]] -= s;
+    }
+  }
+}
+
+__global__ void k_grad_weights(int32_t B, const LzState *__restrict__ st,
+                               const double *__restrict__ grad_r, double *__restrict__ cw) {
+  const int j = threadIdx.x;
+  if (j >= B) return;
+  const LzState &S = st[j];
+  cw[j] = S.pair >= 0 ? (grad_r ? grad_r[S.pair] : 1.0) * S.c : 0.0;
+}
+
+__global__ void k_to_float(int64_t m, const double *__restrict__ a, float *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) b[i] = (float)a[i];
 }
 
 // beta_{i+1} of every running column and the next scales.
@@ -503,6 +608,11 @@ struct BatchWork {
   double *part = nullptr;  // [Bcap][ldp]
   int32_t ldp = 0;
   double *colsum = nullptr;  // [Bcap]
+  // gradient mode: search directions and potentials (n x B each), edge accumulator
+  void *P = nullptr, *Xp = nullptr;
+  size_t pot_bytes = 0;
+  double *gacc = nullptr;  // [m]
+  double *cw = nullptr;    // [256]
   LzState *st = nullptr;
   ColCtrl *ctrl = nullptr;
   int32_t *qstate = nullptr;       // [4]: queue head, active columns, working iterations, 1
@@ -521,6 +631,10 @@ void batch_free(rd_graph g) {
   dev_free(bw->X[1]);
   dev_free(bw->part);
   dev_free(bw->colsum);
+  dev_free(bw->P);
+  dev_free(bw->Xp);
+  dev_free(bw->gacc);
+  dev_free(bw->cw);
   dev_free(bw->st);
   dev_free(bw->ctrl);
   dev_free(bw->qstate);
@@ -635,7 +749,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
                        bw->part, bw->ldp, bw->grid_short, active);
 }
 
-template <typename VT, int B>
+template <typename VT, int B, bool GRAD>
 static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const RunParams &prm,
                                     const int32_t *ps, const int32_t *pt, rd_result *out,
                                     hipStream_t st, bool prof) {
@@ -648,15 +762,18 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const Ru
   hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
                      bw->grid_short + bw->nlong, bw->colsum, bw->qstate + 1);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
-                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
-  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1);
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
+  hipLaunchKernelGGL((k_update<VT, B, GRAD>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                     g->deg, Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1, (VT *)bw->P,
+                     (VT *)bw->Xp);
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                      bw->st, bw->ctrl, bw->qstate + 1);
 }
 
 // Run all pairs through B slots. Returns the number of iterations enqueued.
-template <typename VT, int B>
+// GRAD: npairs <= B (no refill) and the potentials of the B runs are
+// accumulated in bw->Xp (bw->P, bw->Xp zeroed by the caller).
+template <typename VT, int B, bool GRAD = false>
 static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                            const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
                            bool prof) {
@@ -665,9 +782,10 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   // fill the slots: control with every column idle pops the first B pairs,
   // then the update writes their start vectors (and zeros elsewhere)
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
-                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate);
-  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp, bw->qstate + 1);
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
+  hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                     g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
+                     bw->qstate + 1, (VT *)nullptr, (VT *)nullptr);
   RD_HIP(hipGetLastError());
   int cur = 0;
   int64_t iters = 0;
@@ -675,7 +793,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   const int64_t cap = (int64_t)prm.max_iters * ((npairs + B - 1) / B + 1) + 16;
   for (;;) {
     for (int j = 0; j < chunk; ++j) {
-      enqueue_batch_iteration<VT, B>(g, bw, cur, prm, ps, pt, out, st, prof);
+      enqueue_batch_iteration<VT, B, GRAD>(g, bw, cur, prm, ps, pt, out, st, prof);
       cur ^= 1;
     }
     iters += chunk;
@@ -705,13 +823,67 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
 
+// Edge gradient of sum_p grad_r[p] r(s_p, t_p): pairs in groups of B (one
+// run per group, no refill), potentials accumulated during the run, then one
+// edge pass per group into an FP64 accumulator.
+template <typename VT, int B>
+static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
+                       const int32_t *pt, const double *grad_r, const RunParams &prm0,
+                       rd_result *out, float *grad_w, hipStream_t st) {
+  batch_reserve(g, bw, B, sizeof(VT));
+  const size_t need = (size_t)g->n * B * sizeof(VT);
+  if (need > bw->pot_bytes) {
+    dev_free(bw->P);
+    dev_free(bw->Xp);
+    bw->P = bw->Xp = nullptr;
+    bw->pot_bytes = 0;
+    bw->P = dev_alloc(need);
+    bw->Xp = dev_alloc(need);
+    bw->pot_bytes = need;
+  }
+  if (!bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
+  if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
+  RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
+  for (int32_t off = 0; off < npairs; off += B) {
+    const int32_t nb = std::min<int32_t>(B, npairs - off);
+    RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
+    RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
+    RunParams prm = prm0;
+    prm.npairs = nb;
+    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, false);
+    hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
+                       grad_r ? grad_r + off : nullptr, bw->cw);
+    hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                       g->row_ptr, g->col, g->eid, (const VT *)bw->Xp, (const double *)bw->cw, bw->gacc);
+    RD_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
+                     (const double *)bw->gacc, grad_w);
+  RD_HIP(hipGetLastError());
+}
+
+template <typename VT>
+static void grad_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
+                          const int32_t *pt, const double *grad_r, const RunParams &prm,
+                          rd_result *out, float *grad_w, hipStream_t st) {
+  switch (B) {
+    case 16: return grad_run_t<VT, 16>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+    case 32: return grad_run_t<VT, 32>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+    case 64: return grad_run_t<VT, 64>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+    case 128: return grad_run_t<VT, 128>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+    case 256: return grad_run_t<VT, 256>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+  }
+  throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
+}
+
 // Time of one sparse product at width B (vectors of arbitrary content).
 template <typename VT, int B>
 static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   batch_reserve(g, bw, B, sizeof(VT));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
-  hipLaunchKernelGGL((k_update<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n, g->deg,
-                     (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp, bw->qstate + 3);
+  hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                     g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
+                     bw->qstate + 3, (VT *)nullptr, (VT *)nullptr);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
@@ -845,10 +1017,77 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
   }
 }
 
-rd_status rd_grad_edges(rd_graph g, int32_t, const int32_t *, const int32_t *, const double *,
-                        double, const rd_options *, rd_result *, float *) {
-  if (g) g->err = "rd_grad_edges is not available in this build";
-  return RD_E_ARG;
+rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
+                        const double *grad_r, double eps, const rd_options *o, rd_result *fwd,
+                        float *grad_w) {
+  if (!g || npairs < 0 || !grad_w || (npairs > 0 && (!s || !t))) return RD_E_ARG;
+  std::vector<void *> owned;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    RD_REQUIRE(opt.fixed_k > 0 || eps > 0.0, "eps must be > 0 unless fixed_k is set");
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, o);
+    BatchWork *bw = batch_get(g);
+    const bool dp = opt.flags & RD_DEVICE_PTRS;
+    auto tmp = [&](size_t bytes) {
+      void *p = dev_alloc(bytes);
+      owned.push_back(p);
+      return p;
+    };
+    const int32_t *ds = s, *dt = t;
+    const double *dg = grad_r;
+    rd_result *dout = fwd;
+    float *dgw = grad_w;
+    if (!dp) {
+      if (npairs > 0) {
+        int32_t *pp = (int32_t *)tmp(2 * (size_t)npairs * sizeof(int32_t));
+        RD_HIP(hipMemcpyAsync(pp, s, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        RD_HIP(hipMemcpyAsync(pp + npairs, t, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        ds = pp;
+        dt = pp + npairs;
+        if (grad_r) {
+          double *d = (double *)tmp((size_t)npairs * sizeof(double));
+          RD_HIP(hipMemcpyAsync(d, grad_r, npairs * sizeof(double), hipMemcpyHostToDevice, st));
+          dg = d;
+        }
+      }
+      dout = nullptr;
+      dgw = (float *)tmp((size_t)g->m * sizeof(float));
+    }
+    if (!dout) dout = (rd_result *)tmp(std::max<size_t>(1, npairs) * sizeof(rd_result));
+    if (npairs > 0) {
+      RD_HIP(hipMemsetAsync(bw->flag, 0, sizeof(int32_t), st));
+      hipLaunchKernelGGL(k_check_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->n, ds,
+                         dt, bw->flag);
+      int32_t bad = 0;
+      RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      RD_HIP(hipStreamSynchronize(st));
+      RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+    }
+    int32_t B = opt.block_width;
+    if (B == 0) B = autotune_width(g, bw, opt.precision, std::max(npairs, 1), st);
+    RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
+               "block_width must be 0 or one of 16, 32, 64, 128, 256");
+    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
+    if (opt.precision == RD_F64)
+      grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st);
+    else
+      grad_dispatch<float>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st);
+    if (!dp) {
+      if (fwd && npairs > 0)
+        RD_HIP(hipMemcpyAsync(fwd, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
+      RD_HIP(hipMemcpyAsync(grad_w, dgw, (size_t)g->m * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    RD_HIP(hipStreamSynchronize(st));
+    for (void *p : owned) dev_free(p);
+    return RD_OK;
+  } catch (const RdError &e) {
+    (void)hipDeviceSynchronize();
+    for (void *p : owned) dev_free(p);
+    g->err = e.msg;
+    return e.code;
+  }
 }
 
 }  // extern "C"
