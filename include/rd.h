@@ -67,13 +67,20 @@ typedef struct {
   int32_t max_iters;   /* iteration cap; 0 = min(n, 100000) */
   int32_t fixed_k;     /* > 0: run exactly k iterations, as Algorithm 3 states
                           it (eps is ignored; an exact breakdown still stops) */
-  int32_t delay;       /* window d of the stopping estimator; 0 = 4 */
+  int32_t delay;       /* window d of the stopping estimator; 0 = 8 */
   int32_t block_width; /* rd_query_batch: columns per sweep, 0 = autotuned */
   int32_t err_mode;    /* 0: eps is relative to r_hat; 1: eps is absolute
                           (the paper's error notion, Definition of
                           epsilon-absolute error) */
   uint32_t flags;      /* RD_DEVICE_PTRS: the array arguments of rd_query_batch
                           and rd_grad_edges are device pointers */
+  int32_t refine;      /* rd_query_batch only. 1: report the FP64 energy
+                          J = 2 b^T phi - phi^T L phi (b = e_s - e_t) of the
+                          potential phi accumulated by the run (Algorithm 5,
+                          line 1) instead of r_hat. J <= r, and r - J equals
+                          the squared energy-norm error of phi, so rounding in
+                          FP32 vectors enters only to second order. Pairs run
+                          in groups of block_width without refill. */
   void *stream;        /* hipStream_t, NULL = the handle's stream */
 } rd_options;
 

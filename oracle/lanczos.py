@@ -14,7 +14,8 @@ The steps follow Section 3 in the paper's order and notation:
   (the three-term recurrence, Eq. lz_recurrence);
 * output r_hat = (1/d_s + 1/d_t) e_1^T (I - T)^{-1} e_1 with T the k x k
   tridiagonal matrix of alpha_1..alpha_k and beta_2..beta_k (Eq.
-  approx_formula). Here the k x k system is solved densely, as written.
+  approx_formula). Here the k x k tridiagonal system is solved directly
+  (LAPACK banded solver) after every iteration.
 
 The paper runs a fixed number k of iterations. For a tolerance-driven run the
 oracle applies the stopping rule `stop_rule` below, which the paper does not
@@ -30,6 +31,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 BREAKDOWN_REL = 1e-13
@@ -52,15 +54,19 @@ def tridiag_solve_e1(alpha, beta) -> float:
     """e_1^T (I - T)^{-1} e_1 with T = tridiag(beta[1:], alpha, beta[1:]).
 
     `alpha` holds alpha_1..alpha_k, `beta` holds beta_1..beta_k (beta[0] = beta_1
-    = 0 is unused). Dense solve, as the definition reads."""
+    = 0 is unused). The k x k system (I - T) y = e_1 is solved directly by
+    LAPACK's banded solver (the matrix is tridiagonal), so long runs stay
+    O(k) per step."""
     k = len(alpha)
-    T = np.diag(np.asarray(alpha, dtype=np.float64))
+    ab = np.zeros((3, k))
+    ab[1] = 1.0 - np.asarray(alpha, dtype=np.float64)
     if k > 1:
-        off = np.asarray(beta[1:k], dtype=np.float64)
-        T += np.diag(off, 1) + np.diag(off, -1)
+        off = -np.asarray(beta[1:k], dtype=np.float64)
+        ab[0, 1:] = off
+        ab[2, :-1] = off
     e1 = np.zeros(k)
     e1[0] = 1.0
-    return float(np.linalg.solve(np.eye(k) - T, e1)[0])
+    return float(sla.solve_banded((1, 1), ab, e1)[0])
 
 
 def stop_rule(rhat, tol: float, delay: int) -> tuple:
@@ -113,7 +119,7 @@ class LanczosRun:
     V: list = field(default_factory=list)  # v_1..v_k when keep_vectors
 
 
-def lanczos_rd(g, s: int, t: int, k: int | None = None, tol: float | None = None, delay: int = 4,
+def lanczos_rd(g, s: int, t: int, k: int | None = None, tol: float | None = None, delay: int = 8,
                max_iters: int | None = None, keep_vectors: bool = False, A=None, d=None) -> LanczosRun:
     """Algorithm 3 for the pair (s, t): fixed k iterations when `k` is given,
     otherwise iterate until `stop_rule(tol, delay)` holds or `max_iters`."""

@@ -263,10 +263,11 @@ rd_options resolve_options(rd_graph g, const rd_options *o) {
   RD_REQUIRE(r.precision == RD_F64 || r.precision == RD_F32, "precision must be RD_F64 or RD_F32");
   RD_REQUIRE(r.max_iters >= 0 && r.fixed_k >= 0, "max_iters and fixed_k must be >= 0");
   if (r.max_iters == 0) r.max_iters = std::min<int32_t>(g->n, 100000);
-  if (r.delay == 0) r.delay = 4;
+  if (r.delay == 0) r.delay = 8;
   RD_REQUIRE(r.delay >= 1 && r.delay <= RD_HIST - 2, "delay must be in [1, 14]");
   RD_REQUIRE(r.err_mode == 0 || r.err_mode == 1, "err_mode must be 0 or 1");
   RD_REQUIRE(r.block_width >= 0 && r.block_width <= 256, "block_width must be in [0, 256]");
+  RD_REQUIRE(r.refine == 0 || r.refine == 1, "refine must be 0 or 1");
   return r;
 }
 
@@ -332,7 +333,8 @@ void rd_default_options(rd_options *o) {
   o->precision = RD_F64;
   o->max_iters = 0;
   o->fixed_k = 0;
-  o->delay = 4;
+  o->delay = 8;
+  o->refine = 0;
   o->block_width = 0;
   o->err_mode = 0;
   o->flags = 0;

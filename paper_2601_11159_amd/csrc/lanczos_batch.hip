@@ -513,6 +513,54 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
   }
 }
 
+// Per-column energy of the accumulated potentials, sum_e w_e (X[u,p] - X[v,p])^2
+// in FP64, as per-block column partials (each edge once, from its smaller end).
+template <typename VT, int B, bool WEIGHTED>
+__global__ __launch_bounds__(SHORT_THREADS) void k_energy(
+    int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ w64, const VT *__restrict__ X, double *__restrict__ part,
+    int32_t ldp) {
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  using V = VecN<VT, VEC>;
+  __shared__ double sm[(SHORT_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  double acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t u = gw * S::RPW + sub; u < n; u += nwv * S::RPW) {
+    const V xu = vload<VT, VEC>(X + (size_t)u * B + c0);
+    const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
+    for (int32_t p = pb; p < pe; ++p) {
+      const int32_t v = col[p];
+      if (v <= u) continue;
+      const V xv = vload<VT, VEC>(X + (size_t)v * B + c0);
+      const double we = WEIGHTED ? w64[p] : 1.0;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        const double d = (double)xu.v[k] - (double)xv.v[k];
+        acc[k] += we * d * d;
+      }
+    }
+  }
+  block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
+}
+
+// r = J(phi) = 2 (phi_s - phi_t) - phi^T L phi with phi = sqrt(c) X[:, j] (FP64).
+template <typename VT, int B>
+__global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restrict__ X,
+                             const double *__restrict__ energy, rd_result *__restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= B) return;
+  const LzState &S = st[j];
+  if (S.pair < 0) return;
+  const double xs = (double)X[(size_t)S.s * B + j], xt = (double)X[(size_t)S.t * B + j];
+  out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
+}
+
 __global__ void k_grad_weights(int32_t B, const LzState *__restrict__ st,
                                const double *__restrict__ grad_r, double *__restrict__ cw) {
   const int j = threadIdx.x;
@@ -826,10 +874,13 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
 // Edge gradient of sum_p grad_r[p] r(s_p, t_p): pairs in groups of B (one
 // run per group, no refill), potentials accumulated during the run, then one
 // edge pass per group into an FP64 accumulator.
+// grad_w == nullptr: refinement mode - instead of the edge gradient, each
+// group's results get r = J(phi), the FP64 energy of its potentials.
 template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
                        rd_result *out, float *grad_w, hipStream_t st) {
+  const bool refine = grad_w == nullptr;
   batch_reserve(g, bw, B, sizeof(VT));
   const size_t need = (size_t)g->n * B * sizeof(VT);
   if (need > bw->pot_bytes) {
@@ -841,9 +892,9 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     bw->Xp = dev_alloc(need);
     bw->pot_bytes = need;
   }
-  if (!bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
+  if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
-  RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
+  if (!refine) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
   for (int32_t off = 0; off < npairs; off += B) {
     const int32_t nb = std::min<int32_t>(B, npairs - off);
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
@@ -851,15 +902,33 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     RunParams prm = prm0;
     prm.npairs = nb;
     batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, false);
-    hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
-                       grad_r ? grad_r + off : nullptr, bw->cw);
-    hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                       g->row_ptr, g->col, g->eid, (const VT *)bw->Xp, (const double *)bw->cw, bw->gacc);
+    if (refine) {
+      if (g->unit)
+        hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                           g->n, g->row_ptr, g->col, (const double *)nullptr, (const VT *)bw->Xp,
+                           bw->part, bw->ldp);
+      else
+        hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                           g->n, g->row_ptr, g->col, (const double *)g->w64, (const VT *)bw->Xp,
+                           bw->part, bw->ldp);
+      hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
+                         bw->cw, bw->qstate + 3);
+      hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
+                         (const VT *)bw->Xp, (const double *)bw->cw, out + off);
+    } else {
+      hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
+                         grad_r ? grad_r + off : nullptr, bw->cw);
+      hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                         g->row_ptr, g->col, g->eid, (const VT *)bw->Xp, (const double *)bw->cw,
+                         bw->gacc);
+    }
     RD_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
-                     (const double *)bw->gacc, grad_w);
-  RD_HIP(hipGetLastError());
+  if (!refine) {
+    hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
+                       (const double *)bw->gacc, grad_w);
+    RD_HIP(hipGetLastError());
+  }
 }
 
 template <typename VT>
@@ -999,10 +1068,17 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
     const bool prof = opt.flags & RD_PROFILE;
-    if (opt.precision == RD_F64)
+    if (opt.refine) {
+      // groups of B pairs with potentials, r reported as the FP64 energy
+      if (opt.precision == RD_F64)
+        grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st);
+      else
+        grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st);
+    } else if (opt.precision == RD_F64) {
       batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
-    else
+    } else {
       batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
+    }
     if (!dp) {
       RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
     }

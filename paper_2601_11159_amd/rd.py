@@ -47,6 +47,7 @@ class RdOptions(ctypes.Structure):
         ("block_width", ctypes.c_int32),
         ("err_mode", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("refine", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

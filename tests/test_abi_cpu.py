@@ -34,7 +34,7 @@ def test_status_strings_without_gpu():
 
 def test_default_options_layout():
     o = rd.rd_default_options()
-    assert o.precision == rd.RD_F64 and o.delay == 4 and o.fixed_k == 0 and o.flags == 0
+    assert o.precision == rd.RD_F64 and o.delay == 8 and o.fixed_k == 0 and o.flags == 0 and o.refine == 0
 
 
 def test_generators_deterministic_and_simple():

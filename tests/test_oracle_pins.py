@@ -326,3 +326,13 @@ def test_stop_rule_meets_tolerance_on_grid():
         assert run.converged
         assert (truth[p] - run.r) / truth[p] <= 1e-8
         assert run.r <= truth[p] * (1 + 1e-12)
+
+
+def test_tridiagonal_solve_matches_dense_inverse():
+    # the banded solve of (I - T) y = e_1 against the explicit inverse
+    rng = np.random.default_rng(3)
+    k = 40
+    alpha = rng.uniform(-0.5, 0.5, k)
+    beta = np.concatenate([[0.0], rng.uniform(0.05, 0.4, k - 1)])
+    T = LZ.tridiag_matrix(alpha, beta)
+    assert LZ.tridiag_solve_e1(alpha, beta) == pytest.approx(np.linalg.inv(np.eye(k) - T)[0, 0], rel=1e-12)
