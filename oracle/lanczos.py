@@ -78,31 +78,32 @@ def stop_rule(rhat, tol: float, delay: int) -> tuple:
     With window d = min(delay, k - 2) (k >= 3 is required):
 
         inc_now  = r_hat_k - r_hat_{k-1}
+        inc_prev = r_hat_{k-1} - r_hat_{k-2}
         inc_then = r_hat_{k-d} - r_hat_{k-d-1}
-        span     = r_hat_k - r_hat_{k-d}
-        q        = (inc_now / inc_then)^(1/d)     (per-step contraction)
+        q        = (inc_now / inc_then)^(1/d)     (mean per-step contraction)
 
-    If both increments are positive: q >= 1 gives no estimate (infinite);
-    otherwise q is capped at 0.9999 and the remaining error is estimated by
-    the geometric tail est = max(span * q / (1 - q), inc_now). If either
-    increment is not positive the sequence has reached its rounding floor and
-    est = |span| + |inc_now|. The run stops once est <= tol * r_hat_k.
+    If both inc_now and inc_then are positive: q >= 1 gives no estimate
+    (infinite); otherwise q is capped at 0.9999 and the remaining error is
+    estimated by eight times the geometric tail of the latest increment,
+    est = max(8 inc_now q / (1 - q), inc_now). If either increment is not
+    positive the sequence has reached its rounding floor and
+    est = |inc_now| + |inc_prev|. The run stops once est <= tol * r_hat_k.
     Returns (stop, est)."""
     k = len(rhat)
     if k < 3:
         return False, np.inf
     d = min(delay, k - 2)
     inc_now = rhat[-1] - rhat[-2]
+    inc_prev = rhat[-2] - rhat[-3]
     inc_then = rhat[-1 - d] - rhat[-2 - d]
-    span = rhat[-1] - rhat[-1 - d]
     if inc_now <= 0.0 or inc_then <= 0.0:
-        est = abs(span) + abs(inc_now)
+        est = abs(inc_now) + abs(inc_prev)
     else:
         q = (inc_now / inc_then) ** (1.0 / d)
         if q >= 1.0:
             return False, np.inf
         q = min(q, 0.9999)
-        est = max(span * q / (1.0 - q), inc_now)
+        est = max(8.0 * inc_now * q / (1.0 - q), inc_now)
     return est <= tol * rhat[-1], est
 
 

@@ -52,7 +52,7 @@ struct ColCtrl {
   double xb;    //                x_i = x_{i-1} + xb p_i
   int32_t mode;  // COL_*
   int32_t s, t;
-  int32_t pad;
+  int32_t prev_sparse;  // the previous vector is q_1 (vs at s, vt at t, zero elsewhere)
 };
 
 template <typename VT, int N>
@@ -115,14 +115,21 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
   __shared__ double sm[(SHORT_THREADS / 64) * B];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
-  VT sig[VEC], pc[VEC];
-  bool hp[VEC];
+  VT sig[VEC], pc[VEC], pvs[VEC], pvt[VEC];
+  int32_t pss[VEC], pst[VEC];
+  bool hp[VEC], psp[VEC];
   double apart[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
-    sig[v] = (VT)ctrl[c0 + v].sig;
-    pc[v] = (VT)ctrl[c0 + v].pc;
-    hp[v] = ctrl[c0 + v].pc != 0.0;
+    const ColCtrl &cc = ctrl[c0 + v];
+    sig[v] = (VT)cc.sig;
+    pc[v] = (VT)cc.pc;
+    hp[v] = cc.pc != 0.0;
+    psp[v] = cc.prev_sparse != 0;
+    pss[v] = cc.s;
+    pst[v] = cc.t;
+    pvs[v] = (VT)cc.vs;
+    pvt[v] = (VT)cc.vt;
     apart[v] = 0.0;
   }
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
@@ -164,7 +171,10 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         VT yy = sig[v] * acc[v] * id;
-        if (hp[v]) yy -= pc[v] * up.v[v];
+        if (hp[v]) {
+          const VT prev = psp[v] ? (r == pss[v] ? pvs[v] : (r == pst[v] ? pvt[v] : VT(0))) : up.v[v];
+          yy -= pc[v] * prev;
+        }
         y.v[v] = yy;
         apart[v] += dr * (double)yy * ((double)sig[v] * (double)uc.v[v]);
       }
@@ -239,10 +249,15 @@ __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
     V y;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-      const VT sg = (VT)ctrl[c0 + v].sig;
-      const double pcd = ctrl[c0 + v].pc;
+      const ColCtrl &cc = ctrl[c0 + v];
+      const VT sg = (VT)cc.sig;
+      const double pcd = cc.pc;
       VT yy = sg * tot[v] * id;
-      if (pcd != 0.0) yy -= (VT)pcd * up.v[v];
+      if (pcd != 0.0) {
+        const VT prev =
+            cc.prev_sparse ? (r == cc.s ? (VT)cc.vs : (r == cc.t ? (VT)cc.vt : VT(0))) : up.v[v];
+        yy -= (VT)pcd * prev;
+      }
       y.v[v] = yy;
       apart[v] = dr * (double)yy * ((double)sg * (double)uc.v[v]);
     }
@@ -354,6 +369,7 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       cc.coef = 0.0;
       cc.vs = rc / deg[s];
       cc.vt = -rc / deg[t];
+      cc.prev_sparse = 0;
       cc.s = s;
       cc.t = t;
       active = 1;
@@ -372,6 +388,7 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
     } else {
       cc.mode = COL_RUN;
       cc.coef = S.alpha * S.sig_cur;
+      cc.prev_sparse = 0;  // the sparse q_1 was consumed by this iteration's product
       cc.pa = pa;
       cc.xb = xb;
       active = 1;
@@ -444,7 +461,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
         x = y.v[v] - coef[v] * uc.v[v];
         acc[v] += dr * ((double)x * (double)x);
       } else if (mode[v] == COL_REFILL) {
-        x = (r == cs[v]) ? vs[v] : ((r == ct[v]) ? vt[v] : VT(0));
+        x = VT(0);  // the first iteration's vector is scattered by k_first_batch
       } else {
         x = VT(0);
       }
@@ -599,6 +616,63 @@ __global__ __launch_bounds__(COL_THREADS) void k_beta(const double *__restrict__
   }
 }
 
+// First iteration of every refilled column from the adjacency rows of s and t
+// (block j: column j). Writes w_1 into column j of W (zeroed by k_update),
+// completes iteration 1 of the column's scalars, and arms the next product to
+// read the previous vector q_1 analytically. GRAD: p_1 = q_1, x_1 = q_1/delta_1.
+template <typename VT, int B, bool GRAD>
+__global__ __launch_bounds__(256) void k_first_batch(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ w64, const double *__restrict__ deg, VT *__restrict__ W,
+    LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, VT *__restrict__ P, VT *__restrict__ X,
+    const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  const int j = blockIdx.x;
+  if (ctrl[j].mode != COL_REFILL) return;
+  __shared__ double sm[256 / 64 + 2];
+  __shared__ LzState S0;
+  if (threadIdx.x == 0) S0 = st[j];
+  __syncthreads();
+  const int32_t s = S0.s, t = S0.t;
+  double a1, bb;
+  first_iteration(
+      row_ptr, col, w64, deg, s, t, S0.c,
+      [&](int32_t u, double val) {
+        const VT x = (VT)val;
+        W[(size_t)u * B + j] = x;
+        return (double)x;
+      },
+      sm, a1, bb);
+  if (threadIdx.x == 0) {
+    LzState S = S0;
+    ColCtrl cc = ctrl[j];
+    scalar_after_alpha(S, a1, nullptr, nullptr);
+    const bool advanced = S.k == 1;
+    if (S.status == LZ_RUNNING) scalar_after_beta(S, bb, nullptr);
+    if (GRAD && advanced) {
+      const double rc = 1.0 / sqrt(S.c);
+      const double q1s = rc / deg[s], q1t = -rc / deg[t];
+      P[(size_t)s * B + j] = (VT)q1s;
+      P[(size_t)t * B + j] = (VT)q1t;
+      X[(size_t)s * B + j] = (VT)(q1s / S.delta);
+      X[(size_t)t * B + j] = (VT)(q1t / S.delta);
+    }
+    cc.mode = COL_RUN;
+    cc.coef = 0.0;
+    if (S.status == LZ_RUNNING) {
+      cc.sig = S.sig_cur;     // 1 / beta_2
+      cc.pc = S.prev_coef;    // beta_2 (q_1 is stored with scale 1)
+      cc.prev_sparse = 1;     // cc.vs, cc.vt hold q_1 at s and t
+    } else {
+      cc.sig = 0.0;  // finished after one iteration: retired by the next control step
+      cc.pc = 0.0;
+      cc.prev_sparse = 0;
+    }
+    st[j] = S;
+    ctrl[j] = cc;
+  }
+}
+
 __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__restrict__ ctrl,
                               int32_t *__restrict__ qstate) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -616,7 +690,7 @@ __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__re
     cc.mode = COL_IDLE;
     cc.s = -1;
     cc.t = -1;
-    cc.pad = 0;
+    cc.prev_sparse = 0;
     ctrl[j] = cc;
   }
   if (j == 0) {
@@ -798,6 +872,13 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
 }
 
 template <typename VT, int B, bool GRAD>
+static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
+  hipLaunchKernelGGL((k_first_batch<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->row_ptr, g->col,
+                     (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (VT *)bw->P, (VT *)bw->Xp,
+                     bw->qstate + 1);
+}
+
+template <typename VT, int B, bool GRAD>
 static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const RunParams &prm,
                                     const int32_t *ps, const int32_t *pt, rd_result *out,
                                     hipStream_t st, bool prof) {
@@ -816,6 +897,7 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const Ru
                      (VT *)bw->Xp);
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                      bw->st, bw->ctrl, bw->qstate + 1);
+  launch_first<VT, B, GRAD>(g, bw, Y, st);
 }
 
 // Run all pairs through B slots. Returns the number of iterations enqueued.
@@ -834,6 +916,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
                      bw->qstate + 1, (VT *)nullptr, (VT *)nullptr);
+  launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
   RD_HIP(hipGetLastError());
   int cur = 0;
   int64_t iters = 0;

@@ -31,23 +31,25 @@ __device__ __forceinline__ T block_sum(T x, T *sm) {
 
 // Stopping estimate of the remaining error of r_hat_k from the recent values
 // (reading of the paper, which fixes k): with window d = min(delay, k-2),
-// inc_now = r_k - r_{k-1}, inc_then = r_{k-d} - r_{k-d-1}, span = r_k - r_{k-d}
-// and per-step contraction q = (inc_now/inc_then)^(1/d): the geometric tail
-// max(span q/(1-q), inc_now) with q capped at 0.9999; infinite when q >= 1;
-// |span| + |inc_now| once an increment is not positive (rounding floor).
+// inc_now = r_k - r_{k-1}, inc_prev = r_{k-1} - r_{k-2},
+// inc_then = r_{k-d} - r_{k-d-1} and mean per-step contraction
+// q = (inc_now/inc_then)^(1/d): eight times the geometric tail of the latest
+// increment, max(8 inc_now q/(1-q), inc_now), with q capped at 0.9999;
+// infinite when q >= 1; |inc_now| + |inc_prev| once an increment is not
+// positive (rounding floor).
 __device__ __forceinline__ double stop_estimate(const LzState &S) {
   const int k = S.k;
   if (k < 3) return INFINITY;
   const int d = min(S.delay, k - 2);
   auto h = [&](int j) { return S.hist[(j - 1) % RD_HIST]; };  // r_hat_j, 1-based
   const double inow = h(k) - h(k - 1);
+  const double iprev = h(k - 1) - h(k - 2);
   const double ithen = h(k - d) - h(k - d - 1);
-  const double span = h(k) - h(k - d);
-  if (inow <= 0.0 || ithen <= 0.0) return fabs(span) + fabs(inow);
+  if (inow <= 0.0 || ithen <= 0.0) return fabs(inow) + fabs(iprev);
   double q = pow(inow / ithen, 1.0 / (double)d);
   if (q >= 1.0) return INFINITY;
   q = fmin(q, 0.9999);
-  return fmax(span * q / (1.0 - q), inow);
+  return fmax(8.0 * inow * q / (1.0 - q), inow);
 }
 
 // Iteration i = S.k + 1 has produced alpha_i. Extend the LDL^T factorisation
@@ -135,6 +137,78 @@ __device__ __forceinline__ void state_start(LzState &S, int32_t s, int32_t t, do
   S.s = s;
   S.t = t;
   S.pair = pair;
+}
+
+// Position of `target` in the ascending adjacency row r, or -1.
+__device__ __forceinline__ int32_t row_find(const int32_t *__restrict__ row_ptr,
+                                            const int32_t *__restrict__ col, int32_t r,
+                                            int32_t target) {
+  int32_t lo = row_ptr[r], hi = row_ptr[r + 1];
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    const int32_t c = col[mid];
+    if (c == target) return mid;
+    if (c < target) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+// The first iteration of Algorithm 3 computed from the adjacency rows of s and
+// t only: q_1 = (e_s/d_s - e_t/d_t)/sqrt(c) has two non-zeros, so
+// y_1 = D^{-1} W q_1 lives on N(s) u N(t), alpha_1 = <y_1, q_1>_D involves
+// rows s and t alone, and w_1 = y_1 - alpha_1 q_1 lives on N(s) u N(t) u {s, t}.
+// Every entry of w_1 is passed once to store(u, value) (which returns the value
+// as stored, e.g. rounded to FP32); the block returns alpha_1 and
+// ||w_1||_D^2 (summed in a fixed order) in every thread. All threads of the
+// block must call it. `sm` needs blockDim.x/64 + 2 doubles.
+template <typename Store>
+__device__ void first_iteration(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                const double *__restrict__ w64, const double *__restrict__ deg,
+                                int32_t s, int32_t t, double c, Store store, double *sm,
+                                double &alpha1, double &bb) {
+  const double rc = 1.0 / sqrt(c);
+  const double ds = deg[s], dt = deg[t];
+  const double q1s = rc / ds, q1t = -rc / dt;
+  const int nw = blockDim.x >> 6;
+  if (threadIdx.x == 0) {
+    const int32_t p = row_find(row_ptr, col, s, t);
+    const double wst = p < 0 ? 0.0 : (w64 ? w64[p] : 1.0);
+    const double y1s = wst * q1t / ds, y1t = wst * q1s / dt;
+    sm[nw] = ds * y1s * q1s + dt * y1t * q1t;
+    sm[nw + 1] = p < 0 ? 0.0 : 1.0;
+  }
+  __syncthreads();
+  const double a1 = sm[nw];
+  const bool adjacent = sm[nw + 1] != 0.0;
+  double acc = 0.0;
+  // u in N(s): y_1[u] = (w_us q1s + w_ut q1t)/d_u, the second term if u ~ t
+  for (int32_t p = row_ptr[s] + threadIdx.x; p < row_ptr[s + 1]; p += blockDim.x) {
+    const int32_t u = col[p];
+    double val = (w64 ? w64[p] : 1.0) * q1s;
+    const int32_t pt = row_find(row_ptr, col, t, u);
+    if (pt >= 0) val += (w64 ? w64[pt] : 1.0) * q1t;
+    val /= deg[u];
+    if (u == t) val -= a1 * q1t;
+    const double stored = store(u, val);
+    acc += deg[u] * stored * stored;
+  }
+  // u in N(t) \ N(s)
+  for (int32_t p = row_ptr[t] + threadIdx.x; p < row_ptr[t + 1]; p += blockDim.x) {
+    const int32_t u = col[p];
+    if (row_find(row_ptr, col, s, u) >= 0) continue;
+    double val = (w64 ? w64[p] : 1.0) * q1t / deg[u];
+    if (u == s) val -= a1 * q1s;
+    const double stored = store(u, val);
+    acc += deg[u] * stored * stored;
+  }
+  // s and t themselves when they are not neighbours (then y_1[s] = y_1[t] = 0)
+  if (threadIdx.x == 0 && !adjacent) {
+    const double vs = store(s, -a1 * q1s);
+    const double vt = store(t, -a1 * q1t);
+    acc += ds * vs * vs + dt * vt * vt;
+  }
+  bb = block_sum(acc, sm);
+  alpha1 = a1;
 }
 
 __host__ __device__ inline rd_status status_of(int32_t st) {

@@ -173,9 +173,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(const double *__res
 
 // q_1 = (e_s/d_s - e_t/d_t)/sqrt(c), c = 1/d_s + 1/d_t (v_1 of Algorithm 3 in the scaled basis).
 template <typename VT>
-__global__ void k_init(int32_t n, VT *__restrict__ U, const double *__restrict__ deg, int32_t s,
-                       int32_t t, double tol, int32_t max_iters, int32_t fixed_k, int32_t delay,
-                       int32_t err_mode, LzState *__restrict__ st) {
+__global__ void k_init(int32_t n, VT *__restrict__ U, VT *__restrict__ U1,
+                       const double *__restrict__ deg, int32_t s, int32_t t, double tol,
+                       int32_t max_iters, int32_t fixed_k, int32_t delay, int32_t err_mode,
+                       LzState *__restrict__ st) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const double c = 1.0 / deg[s] + 1.0 / deg[t];
@@ -184,11 +185,48 @@ __global__ void k_init(int32_t n, VT *__restrict__ U, const double *__restrict__
     if (i == s) x = rc / deg[s];
     if (i == t) x = -rc / deg[t];
     U[i] = (VT)x;
+    U1[i] = VT(0);
     if (i == 0) {
       LzState S;
       state_start(S, s, t, c, tol, max_iters, fixed_k, delay, err_mode, 0);
       *st = S;
     }
+  }
+}
+
+// Iteration 1 from the adjacency rows of s and t (q_1 has two non-zeros):
+// w_1 is scattered into U1 (zeroed by k_init), then alpha_1 and beta_2 go
+// through the same scalar update as every later iteration.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_first(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col,
+                                               const double *__restrict__ w64,
+                                               const double *__restrict__ deg, VT *__restrict__ U1,
+                                               LzState *__restrict__ st, double *tr_alpha,
+                                               double *tr_beta, double *tr_rhat) {
+  __shared__ double sm[256 / 64 + 2];
+  __shared__ int32_t s, t;
+  __shared__ double c;
+  if (threadIdx.x == 0) {
+    s = st->s;
+    t = st->t;
+    c = st->c;
+  }
+  __syncthreads();
+  double a1, bb;
+  first_iteration(
+      row_ptr, col, w64, deg, s, t, c,
+      [&](int32_t u, double val) {
+        const VT x = (VT)val;
+        U1[u] = x;
+        return (double)x;
+      },
+      sm, a1, bb);
+  if (threadIdx.x == 0) {
+    LzState S = *st;
+    scalar_after_alpha(S, a1, tr_alpha, tr_rhat);
+    if (S.status == LZ_RUNNING) scalar_after_beta(S, bb, tr_beta);
+    *st = S;
   }
 }
 
@@ -280,11 +318,15 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
                         double *tr_rhat) {
   PlainWork *pw = plain_get(g);
   hipLaunchKernelGGL(k_init<VT>, dim3((g->n + 255) / 256), dim3(256), 0, st, g->n, (VT *)pw->U[0],
-                     g->deg, s, t, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, pw->st);
+                     (VT *)pw->U[1], g->deg, s, t, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode,
+                     pw->st);
+  hipLaunchKernelGGL(k_first<VT>, dim3(1), dim3(256), 0, st, g->row_ptr, g->col,
+                     (const double *)g->w64, g->deg, (VT *)pw->U[1], pw->st, tr_alpha, tr_beta, tr_rhat);
   RD_HIP(hipGetLastError());
   const int cap = o.fixed_k > 0 ? o.fixed_k : o.max_iters;
-  int done_iters = 0, cur = 0;
-  int chunk = o.fixed_k > 0 ? o.fixed_k : std::max(4, std::min(pw->last_k, 64));
+  // iteration 1 is done; the dense iterations start from U[1] (w_1) and U[0] (q_1)
+  int done_iters = 1, cur = 1;
+  int chunk = o.fixed_k > 0 ? o.fixed_k - 1 : std::max(4, std::min(pw->last_k, 64));
   for (;;) {
     const int todo = std::min(chunk, cap - done_iters);
     for (int j = 0; j < todo; ++j) {
@@ -300,7 +342,8 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
   }
   const LzState &S = *pw->st_host;
   // launches after the stopping iteration returned at once: count the first k
-  if (o.flags & RD_PROFILE) g->timer[1].resolve((size_t)S.k);
+  // (iteration 1 has no sparse product: the products of iterations 2..k did work)
+  if (o.flags & RD_PROFILE) g->timer[1].resolve((size_t)std::max(0, S.k - 1));
   int32_t status = S.status;
   if (status == LZ_RUNNING) status = LZ_NOT_CONVERGED;  // cap reached while still running
   out->r = S.rhat;
