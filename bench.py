@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--workload", default="chung_lu_n4M_g2.3_d32_4096pairs", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain-pairs", type=int, default=128)
+    ap.add_argument("--width", type=int, default=0, help="block width (0: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -148,7 +149,7 @@ def main():
 
     # autotune the width once (kept on the handle), then warm up
     t0 = time.time()
-    width = G.tune_width(rd.RD_F32, len(s), stream)
+    width = args.width or G.tune_width(rd.RD_F32, len(s), stream)
     opts_prof = rd.rd_default_options(precision=rd.RD_F32, stream=stream, flags=rd.RD_PROFILE,
                                       block_width=width)
     for _ in range(args.warmup):
@@ -234,7 +235,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "pairs": len(s), "eps_rel": EPS,
                    "precision": "FP32 vectors and sparse products, FP64 Lanczos scalars",
-                   "block_width": width, "block_width_source": "autotuned", "mean_iters": round(float(iters.mean()), 3)},
+                   "block_width": width, "block_width_source": "fixed" if args.width else "autotuned",
+                   "mean_iters": round(float(iters.mean()), 3)},
         "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,
                        "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof},
         "speedup_batched_vs_plain_fp64": round(value / plain_value, 2),

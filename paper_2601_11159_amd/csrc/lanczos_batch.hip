@@ -135,7 +135,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
   for (int32_t it = gw; it < nwi; it += nwv) {
-    const int32_t rb = witem_row[it], re = witem_row[it + 1];
+    const int32_t rb = witem_row[2 * it], re = witem_row[2 * it + 1];
     for (int32_t r = rb + sub; r < re; r += S::RPW) {
       const int32_t pb = row_ptr[r], pe = row_ptr[r + 1];
       if (pe - pb > LONG_DEG) continue;
@@ -720,7 +720,7 @@ struct BatchWork {
   int32_t nwi = 0, nlong = 0;
   int64_t nnz_short = 0;  // adjacency entries of rows handled by k_spmm_short
   int32_t n_short = 0;    // rows handled by k_spmm_short
-  int32_t *witem_row = nullptr;  // [nwi+1]
+  int32_t *witem_row = nullptr;  // [2*nwi]: [begin, end) row range of each work item
   int32_t *long_rows = nullptr;  // [nlong]
   int32_t grid_short = 0, grid_upd = 0;
   // buffers sized for the widest run so far
@@ -774,24 +774,27 @@ static BatchWork *batch_get(rd_graph g) {
   RD_HIP(hipMemcpy(rp.data(), g->row_ptr, (g->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
   std::vector<int32_t> items, longs;
   items.reserve(g->nnz / WAVE_NNZ + 16);
+  // items: [begin, end) ranges of consecutive short rows holding at most
+  // WAVE_NNZ entries (or one row); long rows are listed separately
   int32_t r = 0;
   while (r < g->n) {
-    items.push_back(r);
+    if (rp[r + 1] - rp[r] > LONG_DEG) {
+      longs.push_back(r);
+      ++r;
+      continue;
+    }
+    const int32_t begin = r;
     int64_t acc = 0;
     while (r < g->n) {
       const int32_t len = rp[r + 1] - rp[r];
-      if (len > LONG_DEG) {
-        longs.push_back(r);
-        ++r;
-        continue;
-      }
-      if (acc > 0 && acc + len > WAVE_NNZ) break;
+      if (len > LONG_DEG || (acc > 0 && acc + len > WAVE_NNZ)) break;
       acc += len;
       ++r;
     }
+    items.push_back(begin);
+    items.push_back(r);
   }
-  items.push_back(g->n);
-  bw->nwi = (int32_t)items.size() - 1;
+  bw->nwi = (int32_t)items.size() / 2;
   bw->n_short = g->n - (int32_t)longs.size();
   bw->nnz_short = g->nnz;
   for (int32_t lr : longs) bw->nnz_short -= rp[lr + 1] - rp[lr];
@@ -861,7 +864,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
     RD_HIP(hipEventRecord(ev.second, st));
     const double sv = sizeof(VT);
     g->timer[0].alg_bytes = (double)bw->nnz_short * (4.0 + (WEIGHTED ? sv : 0.0)) +
-                            4.0 * ((double)bw->n_short + bw->nwi + 1) +
+                            4.0 * ((double)bw->n_short + 2.0 * bw->nwi) +
                             sv * B * ((double)g->n + 2.0 * bw->n_short) +
                             (sv + 8.0) * (double)bw->n_short;
   }
