@@ -43,6 +43,197 @@ WORKLOADS = {
     "chung_lu_n500k_g2.3_d32_1024pairs": dict(n=500_000, gamma=2.3, mean_deg=32.0, seed=4,
                                                pairs=1024, pair_seed=4, hub_seed=40),
 }
+# further workloads, one JSON line each (not the default line)
+OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
+                   "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs"]
+
+
+def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
+    d = {"metric": METRIC, "value": round(value, 3), "unit": metric_unit, "n_gpus": 1, "steps": steps,
+         "warmup": warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    d.update(extra)
+    return d
+
+
+def _plain_rate(G, rd, s, t, eps, opts):
+    """Plain single-pair loop over the given pairs: (q/s, results, launches stats)."""
+    import torch
+    G.query(int(s[0]), int(t[0]), eps, opts)
+    G.kernel_stats(1)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    rs, its = [], []
+    for p in range(len(s)):
+        r = G.query(int(s[p]), int(t[p]), eps, opts)
+        rs.append(r.r)
+        its.append(r.iters)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    ms, n, b = G.kernel_stats(1)
+    avg = ms / max(n, 1)
+    roof = {"kernel": "k_spmv (single-pair sparse product)", "bound": "hbm",
+            "achieved": round(b / (avg * 1e-3) / 1e9, 1) if n else None, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if n else None,
+            "traffic": None, "avg_launch_ms": round(avg, 4), "launches": n, "alg_bytes_per_launch": b}
+    return len(s) / dt, np.array(rs), np.array(its), roof, dt
+
+
+def _batch_rate(G, rd, s, t, eps, opts, steps=1):
+    import torch
+    G.query_batch(s[: min(len(s), 64)], t[: min(len(s), 64)], eps, opts)
+    G.kernel_stats(0)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(steps):
+        out = G.query_batch(s, t, eps, opts)
+    torch.cuda.synchronize()
+    dt = (time.time() - t0) / steps
+    ms, n, b = G.kernel_stats(0)
+    avg = ms / max(n, 1)
+    roof = {"kernel": "k_spmm_short (batched sparse product, rows of length <= 1024)", "bound": "hbm",
+            "achieved": round(b / (avg * 1e-3) / 1e9, 1) if n else None, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if n else None,
+            "traffic": None, "avg_launch_ms": round(avg, 4), "launches": n, "alg_bytes_per_launch": b}
+    return len(s) / dt, out, roof, dt
+
+
+def _oracle_sample(g, s, t, tol, budget_s=20.0, max_iters=None):
+    from threadpoolctl import threadpool_limits
+    from oracle import lanczos as LZ
+    t0 = time.time()
+    A, d = LZ.normalized_adjacency(g)
+    setup = time.time() - t0
+    vals, its, secs = [], [], 0.0
+    with threadpool_limits(limits=1):
+        for p in range(len(s)):
+            t1 = time.time()
+            run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=tol, A=A, d=d, max_iters=max_iters)
+            secs += time.time() - t1
+            vals.append(run.r)
+            its.append(run.k)
+            if secs > budget_s:
+                break
+    return np.array(vals), np.array(its), secs, setup
+
+
+def run_other(name, args):
+    """Secondary workloads: one JSON line each."""
+    import torch
+    torch.cuda.set_device(0)
+    from paper_2601_11159_amd import inputs as I
+    from paper_2601_11159_amd import rd
+
+    if name == "grid_64x64_100pairs_fp64":
+        from oracle import dense as D
+        g = I.grid(64, 64)
+        s, t = I.uniform_pairs(g.n, 100, seed=1)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        plain_qps, pr, pit, proof, pdt = _plain_rate(G, rd, s, t, 1e-8, rd.rd_default_options(flags=rd.RD_PROFILE))
+        bq, bout, broof, bdt = _batch_rate(G, rd, s, t, 1e-8, rd.rd_default_options(flags=rd.RD_PROFILE), steps=3)
+        truth = D.rd_all(g, s, t)
+        vals, its, secs, setup = _oracle_sample(g, s, t, 1e-8, budget_s=15.0)
+        line = _line("queries/s", plain_qps, 1, 1, pdt * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 100, "eps_rel": 1e-8,
+                      "path": "plain single-pair FP64 (value); batched FP64 beside it"},
+                     batched_fp64={"value": round(bq, 2), "unit": "queries/s", "roofline": broof},
+                     roofline=dict(proof, note="4,096-node graph: L2-resident, latency-bound"),
+                     cpu_baseline={"value": round(len(vals) / secs, 3), "unit": "queries/s", "cores": 1,
+                                   "kind": "oracle", "sample": f"{len(vals)} of the 100 pairs, numpy Algorithm 3 at 1e-8"},
+                     parity={"plain_max_rel_err_vs_dense": float(np.max(np.abs(pr - truth) / truth)),
+                             "batched_max_rel_err_vs_dense": float(np.max(np.abs(bout['r'] - truth) / truth)),
+                             "mean_iters": float(pit.mean())})
+    elif name == "chung_lu_n1M_g2.1_d20_plain_fp64":
+        g = I.chung_lu(1_000_000, 2.1, 20.0, 2)
+        s, t = I.uniform_pairs(g.n, 1000, seed=2)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        npl = 200
+        plain_qps, pr, pit, proof, pdt = _plain_rate(G, rd, s[:npl], t[:npl], 1e-6,
+                                                     rd.rd_default_options(flags=rd.RD_PROFILE))
+        bq, bout, broof, bdt = _batch_rate(G, rd, s, t, 1e-6, rd.rd_default_options(flags=rd.RD_PROFILE))
+        vals, its, secs, setup = _oracle_sample(g, s[:6], t[:6], 1e-6)
+        k = len(vals)
+        line = _line("queries/s", plain_qps, 1, 1, pdt / npl * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 1000, "eps_rel": 1e-6,
+                      "path": f"plain single-pair FP64 on {npl} pairs (value); batched FP64 on all 1000 beside it"},
+                     batched_fp64={"value": round(bq, 2), "unit": "queries/s", "roofline": broof},
+                     roofline=proof,
+                     cpu_baseline={"value": round(k / secs, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"{k} pairs, numpy Algorithm 3 at 1e-6 ({secs:.1f}s after a {setup:.1f}s build)"},
+                     parity={"plain_max_rel_err_vs_oracle": float(np.max(np.abs(pr[:k] - vals) / vals)),
+                             "batched_max_rel_err_vs_oracle": float(np.max(np.abs(bout['r'][:k] - vals) / vals)),
+                             "mean_iters": float(pit.mean())})
+    elif name == "road_like_2000x2000_256pairs":
+        g = I.road_like(2000, seed=3)
+        s, t = I.uniform_pairs(g.n, 256, seed=3)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        ref = np.array([G.query(int(s[p]), int(t[p]), 1e-10, rd.rd_default_options(max_iters=100000)).r
+                        for p in range(8)])
+        npl = 8
+        plain_qps, pr, pit, proof, pdt = _plain_rate(G, rd, s[:npl], t[:npl], 1e-4,
+                                                     rd.rd_default_options(flags=rd.RD_PROFILE, max_iters=100000))
+        o32 = rd.rd_default_options(precision=rd.RD_F32, refine=1, block_width=64, max_iters=100000,
+                                    flags=rd.RD_PROFILE)
+        bq, bout, broof, bdt = _batch_rate(G, rd, s, t, 1e-5, o32)
+        raw = G.query_batch(s[:64], t[:64], 1e-4, rd.rd_default_options(precision=rd.RD_F32, block_width=64,
+                                                                         max_iters=100000))
+        # CPU oracle: a bounded number of iterations of one pair, scaled to a query
+        from threadpoolctl import threadpool_limits
+        from oracle import lanczos as LZ
+        A, d = LZ.normalized_adjacency(g)
+        with threadpool_limits(limits=1):
+            t1 = time.time()
+            LZ.lanczos_rd(g, int(s[0]), int(t[0]), k=300, A=A, d=d)
+            per_it = (time.time() - t1) / 300
+        line = _line("queries/s", bq, 1, 1, bdt * 1e3, "f32",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256,
+                      "path": "batched FP32 sparse products + FP64 scalars + FP64 energy refinement, eps 1e-5 "
+                              "for the 1e-4 target (value); plain FP64 at 1e-4 on 8 pairs beside it"},
+                     plain_fp64={"value": round(plain_qps, 3), "unit": "queries/s", "mean_iters": float(pit.mean()),
+                                 "roofline": proof},
+                     speedup_batched_vs_plain_fp64=round(bq / plain_qps, 2),
+                     roofline=dict(broof, note="FP32 block of 4M x 64 per vector; refinement adds two vector streams"),
+                     cpu_baseline={"value": round(1.0 / (per_it * float(pit.mean())), 6), "unit": "queries/s",
+                                   "cores": 1, "kind": "oracle",
+                                   "sample": f"300 iterations of numpy Algorithm 3 on one pair ({per_it * 300:.1f}s), "
+                                             f"scaled by the mean FP64 iteration count {pit.mean():.0f}"},
+                     parity={"reference": "plain FP64 GPU at eps 1e-10 on 8 pairs (the oracle's parity on "
+                                          "road-like grids is tested at 300x300)",
+                             "batched_fp32_refined_max_rel_err": float(np.max(np.abs(bout['r'][:8] - ref) / ref)),
+                             "batched_fp32_unrefined_max_rel_err": float(np.max(np.abs(raw['r'][:8] - ref) / ref)),
+                             "plain_fp64_max_rel_err": float(np.max(np.abs(pr - ref) / ref))})
+    elif name == "weighted_chung_lu_n1M_grad_256pairs":
+        g = I.chung_lu(1_000_000, 2.1, 20.0, 2)
+        w = I.lognormal_weights(g.m, 0.0, 1.0, seed=5)
+        s, t = I.uniform_pairs(g.n, 256, seed=6)
+        G = rd.RDGraph(g.n, g.u, g.v, w)
+        o = rd.rd_default_options(precision=rd.RD_F32, block_width=64)
+        G.grad_edges(s[:64], t[:64], None, 1e-6, o)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        fwd, gw = G.grad_edges(s, t, None, 1e-6, o)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        t0 = time.time()
+        out = G.query_batch(s, t, 1e-6, o)
+        torch.cuda.synchronize()
+        fdt = time.time() - t0
+        euler = float(np.dot(w.astype(np.float64), gw.astype(np.float64)))
+        gw_graph = I.Graph(g.n, g.u, g.v, w)
+        vals, its, secs, setup = _oracle_sample(gw_graph, s[:2], t[:2], 1e-6)
+        line = _line("pairs/s (forward + edge gradient)", len(s) / dt, 1, 1, dt * 1e3, "f32",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": 1e-6,
+                      "path": "rd_grad_edges, FP32 vectors, width 64"},
+                     forward_only={"value": round(len(s) / fdt, 2), "unit": "queries/s"},
+                     roofline=None,
+                     cpu_baseline={"value": round(len(vals) / secs, 4), "unit": "queries/s (forward only)",
+                                   "cores": 1, "kind": "oracle",
+                                   "sample": f"{len(vals)} pairs, numpy Algorithm 3 forward at 1e-6"},
+                     parity={"euler_identity_rel_err": abs(euler + float(fwd['r'].sum())) / float(fwd['r'].sum()),
+                             "forward_max_rel_err_vs_oracle": float(np.max(np.abs(fwd['r'][:len(vals)] - vals) / vals))})
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    print(json.dumps(line), flush=True)
 
 
 def log(msg):
@@ -95,7 +286,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chung_lu_n4M_g2.3_d32_4096pairs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="chung_lu_n4M_g2.3_d32_4096pairs",
+                    choices=sorted(WORKLOADS) + OTHER_WORKLOADS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain-pairs", type=int, default=128)
     ap.add_argument("--width", type=int, default=0, help="block width (0: autotuned)")
@@ -125,6 +317,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.workload in OTHER_WORKLOADS:
+        run_other(args.workload, args)
+        return
     from paper_2601_11159_amd import inputs as I
     from paper_2601_11159_amd import rd
 

@@ -54,6 +54,9 @@ typedef enum {
 /* flags */
 #define RD_DEVICE_PTRS 0x1u
 #define RD_PROFILE 0x2u /* rd_options.flags: time the sparse-product launches (see rd_kernel_stats) */
+#define RD_GENERAL_PATH 0x4u /* rd_options.flags: never use the single-workgroup path that
+                                rd_query, rd_query_trace and rd_query_batch (without refine)
+                                take when both n-vectors of a run fit in one workgroup's LDS */
 
 /* weight / vector dtypes */
 #define RD_F64 0

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
                                                           const ColCtrl *__restrict__ ctrl,
                                                           double *__restrict__ part, int32_t ldp,
                                                           const int32_t *__restrict__ active,
-                                                          VT *__restrict__ P, VT *__restrict__ X) {
+                                                          double *__restrict__ P, double *__restrict__ X) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -428,7 +428,8 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
   __shared__ double sm[(SHORT_THREADS / 64) * B];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
-  VT coef[VEC], vs[VEC], vt[VEC], sig[VEC], pa[VEC], xb[VEC];
+  VT coef[VEC], vs[VEC], vt[VEC], sig[VEC];
+  double pa[VEC], xb[VEC];
   int32_t mode[VEC], cs[VEC], ct[VEC];
   bool pot = false;
   double acc[VEC];
@@ -439,8 +440,8 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     vs[v] = (VT)cc.vs;
     vt[v] = (VT)cc.vt;
     sig[v] = (VT)cc.sig;
-    pa[v] = (VT)cc.pa;
-    xb[v] = (VT)cc.xb;
+    pa[v] = cc.pa;
+    xb[v] = cc.xb;
     mode[v] = cc.mode;
     cs[v] = cc.s;
     ct[v] = cc.t;
@@ -470,18 +471,18 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     vstore<VT, VEC>(Y + (size_t)r * B + c0, o);
     if constexpr (GRAD) {
       if (pot) {
-        V pv = vload<VT, VEC>(P + (size_t)r * B + c0);
-        V xv = vload<VT, VEC>(X + (size_t)r * B + c0);
+        VecN<double, VEC> pv = vload<double, VEC>(P + (size_t)r * B + c0);
+        VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)r * B + c0);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           if (mode[v] == COL_RUN || mode[v] == COL_FINAL) {
-            const VT p = sig[v] * uc.v[v] + pa[v] * pv.v[v];
+            const double p = (double)sig[v] * (double)uc.v[v] + pa[v] * pv.v[v];
             pv.v[v] = p;
             xv.v[v] += xb[v] * p;
           }
         }
-        vstore<VT, VEC>(P + (size_t)r * B + c0, pv);
-        vstore<VT, VEC>(X + (size_t)r * B + c0, xv);
+        vstore<double, VEC>(P + (size_t)r * B + c0, pv);
+        vstore<double, VEC>(X + (size_t)r * B + c0, xv);
       }
     }
   }
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
 template <typename VT, int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
     int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const VT *__restrict__ X, const double *__restrict__ cw,
+    const int32_t *__restrict__ eid, const double *__restrict__ X, const double *__restrict__ cw,
     double *__restrict__ gacc) {
   constexpr int VEC = B >= 64 ? B / 64 : 1;
   using V = VecN<VT, VEC>;
@@ -509,18 +510,18 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + (threadIdx.x >> 6);
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
   for (int32_t u = gw; u < n; u += nwv) {
-    V xu;
-    if (on) xu = vload<VT, VEC>(X + (size_t)u * B + c0);
+    VecN<double, VEC> xu;
+    if (on) xu = vload<double, VEC>(X + (size_t)u * B + c0);
     const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
     for (int32_t p = pb; p < pe; ++p) {
       const int32_t v = col[p];
       if (v <= u) continue;  // each edge once, from its smaller end
       double s = 0.0;
       if (on) {
-        const V xv = vload<VT, VEC>(X + (size_t)v * B + c0);
+        const VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)v * B + c0);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
-          const double d = (double)xu.v[k] - (double)xv.v[k];
+          const double d = xu.v[k] - xv.v[k];
           s += w[k] * d * d;
         }
       }
@@ -535,7 +536,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
 template <typename VT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
     int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const double *__restrict__ w64, const VT *__restrict__ X, double *__restrict__ part,
+    const double *__restrict__ w64, const double *__restrict__ X, double *__restrict__ part,
     int32_t ldp) {
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -549,16 +550,16 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
   for (int32_t u = gw * S::RPW + sub; u < n; u += nwv * S::RPW) {
-    const V xu = vload<VT, VEC>(X + (size_t)u * B + c0);
+    const VecN<double, VEC> xu = vload<double, VEC>(X + (size_t)u * B + c0);
     const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
     for (int32_t p = pb; p < pe; ++p) {
       const int32_t v = col[p];
       if (v <= u) continue;
-      const V xv = vload<VT, VEC>(X + (size_t)v * B + c0);
+      const VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)v * B + c0);
       const double we = WEIGHTED ? w64[p] : 1.0;
 #pragma unroll
       for (int k = 0; k < VEC; ++k) {
-        const double d = (double)xu.v[k] - (double)xv.v[k];
+        const double d = xu.v[k] - xv.v[k];
         acc[k] += we * d * d;
       }
     }
@@ -568,13 +569,13 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
 
 // r = J(phi) = 2 (phi_s - phi_t) - phi^T L phi with phi = sqrt(c) X[:, j] (FP64).
 template <typename VT, int B>
-__global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restrict__ X,
+__global__ void k_refine_out(const LzState *__restrict__ st, const double *__restrict__ X,
                              const double *__restrict__ energy, rd_result *__restrict__ out) {
   const int j = threadIdx.x;
   if (j >= B) return;
   const LzState &S = st[j];
   if (S.pair < 0) return;
-  const double xs = (double)X[(size_t)S.s * B + j], xt = (double)X[(size_t)S.t * B + j];
+  const double xs = X[(size_t)S.s * B + j], xt = X[(size_t)S.t * B + j];
   out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
 }
 
@@ -624,7 +625,7 @@ template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(256) void k_first_batch(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ w64, const double *__restrict__ deg, VT *__restrict__ W,
-    LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, VT *__restrict__ P, VT *__restrict__ X,
+    LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, double *__restrict__ P, double *__restrict__ X,
     const int32_t *__restrict__ active) {
   if (*active == 0) return;
   const int j = blockIdx.x;
@@ -652,10 +653,10 @@ __global__ __launch_bounds__(256) void k_first_batch(
     if (GRAD && advanced) {
       const double rc = 1.0 / sqrt(S.c);
       const double q1s = rc / deg[s], q1t = -rc / deg[t];
-      P[(size_t)s * B + j] = (VT)q1s;
-      P[(size_t)t * B + j] = (VT)q1t;
-      X[(size_t)s * B + j] = (VT)(q1s / S.delta);
-      X[(size_t)t * B + j] = (VT)(q1t / S.delta);
+      P[(size_t)s * B + j] = q1s;
+      P[(size_t)t * B + j] = q1t;
+      X[(size_t)s * B + j] = q1s / S.delta;
+      X[(size_t)t * B + j] = q1t / S.delta;
     }
     cc.mode = COL_RUN;
     cc.coef = 0.0;
@@ -877,7 +878,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
 template <typename VT, int B, bool GRAD>
 static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
   hipLaunchKernelGGL((k_first_batch<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->row_ptr, g->col,
-                     (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (VT *)bw->P, (VT *)bw->Xp,
+                     (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (double *)bw->P, (double *)bw->Xp,
                      bw->qstate + 1);
 }
 
@@ -896,8 +897,8 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const Ru
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
   hipLaunchKernelGGL((k_update<VT, B, GRAD>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     g->deg, Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1, (VT *)bw->P,
-                     (VT *)bw->Xp);
+                     g->deg, Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1, (double *)bw->P,
+                     (double *)bw->Xp);
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                      bw->st, bw->ctrl, bw->qstate + 1);
   launch_first<VT, B, GRAD>(g, bw, Y, st);
@@ -918,7 +919,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
-                     bw->qstate + 1, (VT *)nullptr, (VT *)nullptr);
+                     bw->qstate + 1, (double *)nullptr, (double *)nullptr);
   launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
   RD_HIP(hipGetLastError());
   int cur = 0;
@@ -965,10 +966,10 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
 template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
-                       rd_result *out, float *grad_w, hipStream_t st) {
+                       rd_result *out, float *grad_w, hipStream_t st, bool prof) {
   const bool refine = grad_w == nullptr;
   batch_reserve(g, bw, B, sizeof(VT));
-  const size_t need = (size_t)g->n * B * sizeof(VT);
+  const size_t need = (size_t)g->n * B * sizeof(double);  // potentials kept in FP64
   if (need > bw->pot_bytes) {
     dev_free(bw->P);
     dev_free(bw->Xp);
@@ -987,25 +988,25 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
     RunParams prm = prm0;
     prm.npairs = nb;
-    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, false);
+    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
     if (refine) {
       if (g->unit)
         hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->n, g->row_ptr, g->col, (const double *)nullptr, (const VT *)bw->Xp,
+                           g->n, g->row_ptr, g->col, (const double *)nullptr, (const double *)bw->Xp,
                            bw->part, bw->ldp);
       else
         hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->n, g->row_ptr, g->col, (const double *)g->w64, (const VT *)bw->Xp,
+                           g->n, g->row_ptr, g->col, (const double *)g->w64, (const double *)bw->Xp,
                            bw->part, bw->ldp);
       hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                          bw->cw, bw->qstate + 3);
       hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
-                         (const VT *)bw->Xp, (const double *)bw->cw, out + off);
+                         (const double *)bw->Xp, (const double *)bw->cw, out + off);
     } else {
       hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
                          grad_r ? grad_r + off : nullptr, bw->cw);
       hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                         g->row_ptr, g->col, g->eid, (const VT *)bw->Xp, (const double *)bw->cw,
+                         g->row_ptr, g->col, g->eid, (const double *)bw->Xp, (const double *)bw->cw,
                          bw->gacc);
     }
     RD_HIP(hipGetLastError());
@@ -1020,13 +1021,13 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
 template <typename VT>
 static void grad_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
                           const int32_t *pt, const double *grad_r, const RunParams &prm,
-                          rd_result *out, float *grad_w, hipStream_t st) {
+                          rd_result *out, float *grad_w, hipStream_t st, bool prof) {
   switch (B) {
-    case 16: return grad_run_t<VT, 16>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
-    case 32: return grad_run_t<VT, 32>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
-    case 64: return grad_run_t<VT, 64>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
-    case 128: return grad_run_t<VT, 128>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
-    case 256: return grad_run_t<VT, 256>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st);
+    case 16: return grad_run_t<VT, 16>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
+    case 32: return grad_run_t<VT, 32>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
+    case 64: return grad_run_t<VT, 64>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
+    case 128: return grad_run_t<VT, 128>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
+    case 256: return grad_run_t<VT, 256>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
   }
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
@@ -1038,7 +1039,7 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
-                     bw->qstate + 3, (VT *)nullptr, (VT *)nullptr);
+                     bw->qstate + 3, (double *)nullptr, (double *)nullptr);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
@@ -1149,17 +1150,26 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
     RD_HIP(hipStreamSynchronize(st));
     RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
     int32_t B = opt.block_width;
-    if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
-    RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
+    RD_REQUIRE(B == 0 || B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
+    if (!opt.refine && small_eligible(g, opt)) {
+      // both vectors of a run fit in LDS: one workgroup per pair
+      small_run(g, npairs, ds, dt, 0, 0, eps, opt, st, dout, nullptr, nullptr, nullptr);
+      if (!dp)
+        RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
+      RD_HIP(hipStreamSynchronize(st));
+      for (void *p : owned) dev_free(p);
+      return RD_OK;
+    }
+    if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
     const bool prof = opt.flags & RD_PROFILE;
     if (opt.refine) {
       // groups of B pairs with potentials, r reported as the FP64 energy
       if (opt.precision == RD_F64)
-        grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st);
+        grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
       else
-        grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st);
+        grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
     } else if (opt.precision == RD_F64) {
       batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
     } else {
@@ -1233,9 +1243,9 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
     if (opt.precision == RD_F64)
-      grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st);
+      grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st, opt.flags & RD_PROFILE);
     else
-      grad_dispatch<float>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st);
+      grad_dispatch<float>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st, opt.flags & RD_PROFILE);
     if (!dp) {
       if (fwd && npairs > 0)
         RD_HIP(hipMemcpyAsync(fwd, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));

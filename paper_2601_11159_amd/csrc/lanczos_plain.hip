@@ -355,6 +355,17 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
 
 void plain_run(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o, hipStream_t st,
                rd_result *out, double *tr_alpha, double *tr_beta, double *tr_rhat, int32_t) {
+  if (small_eligible(g, o)) {
+    // both vectors fit in LDS: one workgroup runs the whole iteration
+    PlainWork *pw = plain_get(g);
+    rd_result *dres = reinterpret_cast<rd_result *>(pw->st);
+    small_run(g, 1, nullptr, nullptr, s, t, eps, o, st, dres, tr_alpha, tr_beta, tr_rhat);
+    rd_result *hres = reinterpret_cast<rd_result *>(pw->st_host);
+    RD_HIP(hipMemcpyAsync(hres, dres, sizeof(rd_result), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    *out = *hres;
+    return;
+  }
   if (o.precision == RD_F64)
     plain_run_t<double>(g, s, t, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
   else

@@ -129,3 +129,9 @@ void plain_run(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o
 
 // batched path (lanczos_batch.hip)
 void batch_free(rd_graph g);
+
+// one workgroup per pair for graphs whose two vectors fit in LDS (lanczos_small.hip)
+bool small_eligible(rd_graph g, const rd_options &o);
+void small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t s0,
+               int32_t t0, double eps, const rd_options &o, hipStream_t st, rd_result *out,
+               double *tr_alpha, double *tr_beta, double *tr_rhat);

@@ -28,6 +28,7 @@ RD_E_BREAKDOWN = 6
 
 RD_DEVICE_PTRS = 0x1
 RD_PROFILE = 0x2
+RD_GENERAL_PATH = 0x4
 RD_F64 = 0
 RD_F32 = 1
 

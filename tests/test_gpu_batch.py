@@ -18,7 +18,29 @@ from paper_2601_11159_amd import rd  # noqa: E402
 
 
 def _opts(**kw):
+    # these tests exercise the block-column kernels, also on graphs small
+    # enough for the single-workgroup path (tested separately below)
+    kw.setdefault("flags", rd.RD_GENERAL_PATH)
     return rd.rd_default_options(**kw)
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(rd.RD_F64, 1e-10, 1e-8), (rd.RD_F32, 1e-6, 1e-4)])
+def test_single_workgroup_path_batch(prec, tol, bar):
+    # graphs whose two vectors fit in LDS run one workgroup per pair
+    for g in [I.grid(64, 64), I.random_connected(2000, extra=9000, seed=13, weighted=True)]:
+        s, t = I.uniform_pairs(g.n, 120, seed=14)
+        t[7] = s[7]
+        mask = s != t
+        truth = np.zeros(len(s))
+        truth[mask] = D.rd_all(g, s[mask], t[mask])
+        G = rd.RDGraph(g.n, g.u, g.v, g.w)
+        out = G.query_batch(s, t, tol, rd.rd_default_options(precision=prec))
+        assert np.all(out["status"] == rd.RD_OK)
+        assert out["r"][7] == 0.0 and out["iters"][7] == 0
+        err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+        assert err.max() <= bar, (g.name, err.max())
+        gen = G.query_batch(s, t, tol, _opts(precision=prec, block_width=32))
+        assert np.all(np.abs(out["iters"] - gen["iters"]) <= 1)
 
 
 @pytest.mark.parametrize("width", [16, 32, 64, 128, 256])

@@ -18,22 +18,27 @@ from paper_2601_11159_amd import rd  # noqa: E402
 
 F64 = rd.rd_default_options()
 F32 = rd.rd_default_options(precision=rd.RD_F32)
+# small graphs take the single-workgroup path by default; RD_GENERAL_PATH
+# forces the multi-workgroup kernels on the same inputs
+PATHS = {"small": 0, "general": rd.RD_GENERAL_PATH}
 
 
 def _graph(g):
     return rd.RDGraph(g.n, g.u, g.v, g.w)
 
 
-def test_grid64_all_pairs_fp64():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_grid64_all_pairs_fp64(path):
     # 64x64 grid, 100 seeded pairs, tolerance 1e-8; parity 1e-6 against the
     # dense pseudoinverse, and the tolerance itself is met.
     g = I.grid(64, 64)
     s, t = I.uniform_pairs(g.n, 100, seed=1)
     truth = D.rd_all(g, s, t)
     G = _graph(g)
+    opts = rd.rd_default_options(flags=PATHS[path])
     errs = []
     for p in range(len(s)):
-        res = G.query(int(s[p]), int(t[p]), 1e-8, F64)
+        res = G.query(int(s[p]), int(t[p]), 1e-8, opts)
         assert res.status == rd.RD_OK
         errs.append(abs(res.r - truth[p]) / truth[p])
     errs = np.array(errs)
@@ -42,13 +47,14 @@ def test_grid64_all_pairs_fp64():
     assert np.mean(errs <= 1e-8) >= 0.95
 
 
-def test_grid64_step_parity_with_literal_algorithm():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_grid64_step_parity_with_literal_algorithm(path):
     # alpha_i, beta_{i+1}, r_hat_i of the first 50 iterations against the
     # numpy transcription of Algorithm 3.
     g = I.grid(64, 64)
     G = _graph(g)
     for s, t in [(0, 4095), (1000, 1234), (77, 3000)]:
-        a, b, r = G.query_trace(s, t, 50, F64)
+        a, b, r = G.query_trace(s, t, 50, rd.rd_default_options(flags=PATHS[path]))
         run = LZ.lanczos_rd(g, s, t, k=50)
         np.testing.assert_allclose(a, run.alpha, rtol=1e-9, atol=1e-12)
         np.testing.assert_allclose(b, run.beta[1:51], rtol=1e-9)
@@ -104,20 +110,22 @@ def test_paper_toy_graph():
     assert len(r) == 2 and r[-1] == pytest.approx(1.0, rel=1e-13)
 
 
-def test_fixed_k_matches_oracle_fixed_k():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_fixed_k_matches_oracle_fixed_k(path):
     g = I.road_like(40, seed=9)
     s, t = I.uniform_pairs(g.n, 3, seed=2)
     G = _graph(g)
     for p in range(3):
-        res = G.query(int(s[p]), int(t[p]), 0.0, rd.rd_default_options(fixed_k=30))
+        res = G.query(int(s[p]), int(t[p]), 0.0, rd.rd_default_options(fixed_k=30, flags=PATHS[path]))
         run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), k=30)
         assert res.iters == 30
         assert res.r == pytest.approx(run.r, rel=1e-10)
 
 
-def test_iteration_cap_reports_not_converged():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_iteration_cap_reports_not_converged(path):
     g = I.grid(20, 20)
-    res = _graph(g).query(0, 399, 1e-12, rd.rd_default_options(max_iters=3))
+    res = _graph(g).query(0, 399, 1e-12, rd.rd_default_options(max_iters=3, flags=PATHS[path]))
     assert res.status == rd.RD_E_NOT_CONVERGED and res.iters == 3
     run = LZ.lanczos_rd(g, 0, 399, k=3)
     assert res.r == pytest.approx(run.r, rel=1e-12)
