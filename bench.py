@@ -241,8 +241,13 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the source text of k_spmm_short and the helpers it inlines
+    (everything from the block-partials helper to the long-row kernel)."""
     p = os.path.join(ROOT, "paper_2601_11159_amd", "csrc", "lanczos_batch.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    src = open(p).read()
+    a = src.index("// Fold the per-lane column partials")
+    b = src.index("// Rows longer than LONG_DEG")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def load_traffic(workload: str, width: int):
