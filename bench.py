@@ -146,7 +146,7 @@ def run_other(name, args):
     elif name == "chung_lu_n1M_g2.1_d20_plain_fp64":
         g = I.chung_lu(1_000_000, 2.1, 20.0, 2)
         s, t = I.uniform_pairs(g.n, 1000, seed=2)
-        G = rd.RDGraph(g.n, g.u, g.v)
+        G = rd.RDGraph(g.n, g.u, g.v, reorder=bool(args.reorder))
         npl = 200
         plain_qps, pr, pit, proof, pdt = _plain_rate(G, rd, s[:npl], t[:npl], 1e-6,
                                                      rd.rd_default_options(flags=rd.RD_PROFILE))
@@ -155,6 +155,7 @@ def run_other(name, args):
         k = len(vals)
         line = _line("queries/s", plain_qps, 1, 1, pdt / npl * 1e3, "f64",
                      {"workload": name, "n": g.n, "m": g.m, "pairs": 1000, "eps_rel": 1e-6,
+                      "node_order": "decreasing degree (RD_REORDER)" if args.reorder else "as generated",
                       "path": f"plain single-pair FP64 on {npl} pairs (value); batched FP64 on all 1000 beside it"},
                      batched_fp64={"value": round(bq, 2), "unit": "queries/s", "roofline": broof},
                      roofline=proof,
@@ -206,16 +207,23 @@ def run_other(name, args):
         g = I.chung_lu(1_000_000, 2.1, 20.0, 2)
         w = I.lognormal_weights(g.m, 0.0, 1.0, seed=5)
         s, t = I.uniform_pairs(g.n, 256, seed=6)
-        G = rd.RDGraph(g.n, g.u, g.v, w)
-        o = rd.rd_default_options(precision=rd.RD_F32, block_width=64)
+        G = rd.RDGraph(g.n, g.u, g.v, w, reorder=bool(args.reorder))
+        o = rd.rd_default_options(precision=rd.RD_F32, block_width=64, flags=rd.RD_PROFILE)
         G.grad_edges(s[:64], t[:64], None, 1e-6, o)
         torch.cuda.synchronize()
+        G.kernel_stats(2)
         t0 = time.time()
         fwd, gw = G.grad_edges(s, t, None, 1e-6, o)
         torch.cuda.synchronize()
         dt = time.time() - t0
+        gms, gl, gbytes = G.kernel_stats(2)
+        gavg = gms / max(gl, 1)
+        groof = {"kernel": "k_grad_edges (edge pass, FP64 potentials of 64 pairs)", "bound": "hbm",
+                 "achieved": round(gbytes / (gavg * 1e-3) / 1e9, 1) if gl else None, "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(gbytes / (gavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if gl else None,
+                 "traffic": None, "avg_launch_ms": round(gavg, 4), "launches": gl, "alg_bytes_per_launch": gbytes}
         t0 = time.time()
-        out = G.query_batch(s, t, 1e-6, o)
+        out = G.query_batch(s, t, 1e-6, rd.rd_default_options(precision=rd.RD_F32, block_width=64))
         torch.cuda.synchronize()
         fdt = time.time() - t0
         euler = float(np.dot(w.astype(np.float64), gw.astype(np.float64)))
@@ -223,9 +231,10 @@ def run_other(name, args):
         vals, its, secs, setup = _oracle_sample(gw_graph, s[:2], t[:2], 1e-6)
         line = _line("pairs/s (forward + edge gradient)", len(s) / dt, 1, 1, dt * 1e3, "f32",
                      {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": 1e-6,
-                      "path": "rd_grad_edges, FP32 vectors, width 64"},
+                      "path": "rd_grad_edges, FP32 vectors, width 64",
+                      "node_order": "decreasing degree (RD_REORDER)" if args.reorder else "as generated"},
                      forward_only={"value": round(len(s) / fdt, 2), "unit": "queries/s"},
-                     roofline=None,
+                     roofline=groof,
                      cpu_baseline={"value": round(len(vals) / secs, 4), "unit": "queries/s (forward only)",
                                    "cores": 1, "kind": "oracle",
                                    "sample": f"{len(vals)} pairs, numpy Algorithm 3 forward at 1e-6"},
@@ -296,6 +305,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain-pairs", type=int, default=128)
     ap.add_argument("--width", type=int, default=0, help="block width (0: autotuned)")
+    ap.add_argument("--reorder", type=int, default=1, choices=[0, 1],
+                    help="1 (default): build the graph with RD_REORDER (internal ids by decreasing "
+                         "degree); 0: ids as generated")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -339,7 +351,8 @@ def main():
     log(f"graph n={g.n} m={g.m} generated in {time.time() - t0:.1f}s")
 
     t0 = time.time()
-    G = rd.RDGraph(g.n, torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda())
+    G = rd.RDGraph(g.n, torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda(),
+                   reorder=bool(args.reorder))
     torch.cuda.synchronize()
     log(f"rd_init_graph {time.time() - t0:.2f}s")
     ds = torch.from_numpy(s).cuda()
@@ -395,7 +408,7 @@ def main():
     # roofline of the dominant kernel
     avg_ms = k_ms / max(k_launches, 1)
     achieved = k_bytes / (avg_ms * 1e-3) / 1e9 if k_launches else None
-    traffic = load_traffic(args.workload, width) if width else None
+    traffic = load_traffic(args.workload + ("/reordered" if args.reorder else ""), width) if width else None
     roofline = {
         "kernel": "k_spmm_short (batched FP32 sparse product, rows of length <= 1024)",
         "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
@@ -436,6 +449,7 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "pairs": len(s), "eps_rel": EPS,
                    "precision": "FP32 vectors and sparse products, FP64 Lanczos scalars",
                    "block_width": width, "block_width_source": "fixed" if args.width else "autotuned",
+                   "node_order": "decreasing degree (RD_REORDER)" if args.reorder else "as generated",
                    "mean_iters": round(float(iters.mean()), 3)},
         "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,
                        "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof},

@@ -53,10 +53,15 @@ typedef enum {
 
 /* flags */
 #define RD_DEVICE_PTRS 0x1u
-#define RD_PROFILE 0x2u /* rd_options.flags: time the sparse-product launches (see rd_kernel_stats) */
+#define RD_PROFILE 0x2u /* rd_options.flags: time the sparse-product and edge-pass launches (see rd_kernel_stats) */
 #define RD_GENERAL_PATH 0x4u /* rd_options.flags: never use the single-workgroup path that
                                 rd_query, rd_query_trace and rd_query_batch (without refine)
                                 take when both n-vectors of a run fit in one workgroup's LDS */
+
+#define RD_REORDER 0x8u /* rd_init_graph flags: number the nodes internally by decreasing
+                           degree (ties by id) so that the vector entries that the sparse
+                           products gather most often share cache lines. Every argument and
+                           result stays in the caller's node ids and edge order. */
 
 /* weight / vector dtypes */
 #define RD_F64 0
@@ -94,7 +99,7 @@ typedef struct {
   int32_t status; /* RD_OK, RD_E_NOT_CONVERGED or RD_E_BREAKDOWN */
 } rd_result;
 
-/* Fill *o with the defaults (FP64, eps relative, delay 4, autotuned width). */
+/* Fill *o with the defaults (FP64, eps relative, delay 8, autotuned width). */
 void rd_default_options(rd_options *o);
 
 /*
@@ -105,7 +110,8 @@ void rd_default_options(rd_options *o);
  *  w        weights[m] of dtype w_dtype (RD_F64 or RD_F32), finite and > 0;
  *           NULL means unit weights (the unweighted graphs the paper focuses on,
  *           Section 2.1; weighted graphs by the direct generalisation stated there)
- *  flags    RD_DEVICE_PTRS if u, v, w are device pointers
+ *  flags    RD_DEVICE_PTRS if u, v, w are device pointers; RD_REORDER to
+ *           relabel the nodes internally by decreasing degree
  *  out      receives the handle (NULL on failure)
  * Builds the symmetric CSR, weighted degrees d_u = sum_v w_uv in FP64 and the
  * launch schedule on the device; checks connectivity (RD_E_NOT_CONNECTED).
@@ -174,12 +180,16 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
  * Diagnostic: timing of the sparse-product launches recorded by calls made
  * with RD_PROFILE in rd_options.flags, since the previous rd_kernel_stats call
  * (which resets the counters). which = 0: the batched product over rows of
- * length <= 1024 (k_spmm_short); which = 1: the single-pair product (k_spmv).
- * Durations come from HIP events recorded around each launch on the stream it
- * runs on. alg_bytes receives the algorithmic bytes of one launch of the last
- * recorded configuration: adjacency indices (and values, if weighted) of the
- * rows it covers, row offsets, the gathered vector block read once, the
- * previous block read and the result block written, and the degree arrays.
+ * length <= 1024 (k_spmm_short); which = 1: the single-pair product (k_spmv);
+ * which = 2: the edge pass of rd_grad_edges (k_grad_edges, one launch per
+ * group of block_width pairs). Durations come from HIP events recorded around
+ * each launch on the stream it runs on. alg_bytes receives the algorithmic
+ * bytes of one launch of the last recorded configuration. Products: adjacency
+ * indices (and values, if weighted) of the rows covered, row offsets, the
+ * gathered vector block read once, the previous block read and the result
+ * block written, and the degree arrays. Edge pass: its work items, the column
+ * and edge id of every edge, the FP64 accumulator read and written, and the
+ * FP64 potential block read once.
  */
 rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *launches,
                           double *alg_bytes);

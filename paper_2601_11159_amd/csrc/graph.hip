@@ -42,6 +42,38 @@ __global__ void k_validate_keys(int64_t m, int32_t n, const int32_t *__restrict_
   vals[2 * e + 1] = (int32_t)e;
 }
 
+__global__ void k_count_degree(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                               int32_t *__restrict__ cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  atomicAdd(&cnt[u[e]], 1);
+  atomicAdd(&cnt[v[e]], 1);
+}
+
+// ascending sort keys for descending degree
+__global__ void k_degree_keys(int32_t n, const int32_t *__restrict__ cnt, uint32_t *__restrict__ key,
+                              int32_t *__restrict__ ids) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = 0xffffffffu - (uint32_t)cnt[i];
+  ids[i] = i;
+}
+
+// perm[old id] = rank of the old id in the sorted order
+__global__ void k_rank_of(int32_t n, const int32_t *__restrict__ order, int32_t *__restrict__ perm) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) perm[order[r]] = r;
+}
+
+__global__ void k_relabel_keys(int64_t nnz, const int32_t *__restrict__ perm,
+                               uint64_t *__restrict__ keys) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const uint64_t k = keys[p];
+  const uint32_t a = (uint32_t)perm[k >> 32], b = (uint32_t)perm[k & 0xffffffffu];
+  keys[p] = ((uint64_t)a << 32) | b;
+}
+
 __global__ void k_split_keys(int64_t nnz, const uint64_t *__restrict__ keys,
                              int32_t *__restrict__ col, int32_t *__restrict__ flags) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -303,9 +335,70 @@ void KernelTimer::release() {
   used = 0;
 }
 
+__global__ void k_upper_count(int32_t n, const int32_t *__restrict__ row_ptr,
+                              const int32_t *__restrict__ col, int32_t *__restrict__ ub,
+                              int32_t *__restrict__ cnt) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  int32_t lo = row_ptr[u], hi = row_ptr[u + 1];
+  const int32_t re = hi;
+  while (lo < hi) {  // first entry with col > u
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (col[mid] > u) hi = mid;
+    else lo = mid + 1;
+  }
+  ub[u] = lo;
+  cnt[u] = (re - lo + EDGE_CHUNK - 1) / EDGE_CHUNK;
+}
+
+__global__ void k_upper_fill(int32_t n, const int32_t *__restrict__ row_ptr,
+                             const int32_t *__restrict__ ub, const int32_t *__restrict__ cnt,
+                             const int32_t *__restrict__ off, int4 *__restrict__ chunk) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t re = row_ptr[u + 1], nc = cnt[u], o = off[u];
+  int32_t p = ub[u];
+  for (int32_t c = 0; c < nc; ++c, p += EDGE_CHUNK) chunk[o + c] = make_int4(u, p, min(p + EDGE_CHUNK, re), 0);
+}
+
+void edge_chunks(rd_graph g, hipStream_t st) {
+  if (g->echunk) return;
+  const int32_t n = g->n;
+  std::vector<void *> tmp;
+  try {
+    int32_t *buf = (int32_t *)dev_alloc(3 * (size_t)n * sizeof(int32_t));
+    tmp.push_back(buf);
+    int32_t *ub = buf, *cnt = buf + n, *off = buf + 2 * (size_t)n;
+    hipLaunchKernelGGL(k_upper_count, dim3(grid_for(n, 256)), dim3(256), 0, st, n, g->row_ptr, g->col,
+                       ub, cnt);
+    size_t tb = 0;
+    RD_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, n, st));
+    void *scan_tmp = dev_alloc(tb);
+    tmp.push_back(scan_tmp);
+    RD_HIP(hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, cnt, off, n, st));
+    int32_t last[2];
+    RD_HIP(hipMemcpyAsync(&last[0], off + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipMemcpyAsync(&last[1], cnt + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    const int32_t nch = last[0] + last[1];
+    int4 *ch = (int4 *)dev_alloc(std::max<size_t>(1, nch) * sizeof(int4));
+    tmp.push_back(ch);
+    hipLaunchKernelGGL(k_upper_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, n, g->row_ptr,
+                       (const int32_t *)ub, (const int32_t *)cnt, (const int32_t *)off, ch);
+    RD_HIP(hipGetLastError());
+    RD_HIP(hipStreamSynchronize(st));
+    tmp.pop_back();
+    g->echunk = ch;
+    g->nch = nch;
+  } catch (...) {
+    for (void *p : tmp) dev_free(p);
+    throw;
+  }
+  for (void *p : tmp) dev_free(p);
+}
+
 static void free_graph_memory(rd_graph g) {
-  g->timer[0].release();
-  g->timer[1].release();
+  for (KernelTimer &k : g->timer) k.release();
   plain_free(g);
   batch_free(g);
   dev_free(g->row_ptr);
@@ -319,6 +412,8 @@ static void free_graph_memory(rd_graph g) {
   dev_free(g->deg32);
   dev_free(g->blk_row);
   dev_free(g->blk_lanes);
+  dev_free(g->perm);
+  dev_free(g->echunk);
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
 }
 
@@ -361,7 +456,7 @@ const char *rd_last_error(rd_graph g) { return g ? g->err.c_str() : g_init_error
 
 rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *launches,
                           double *alg_bytes) {
-  if (!g || which < 0 || which > 1) return RD_E_ARG;
+  if (!g || which < 0 || which > 2) return RD_E_ARG;
   KernelTimer &k = g->timer[which];
   if (total_ms) *total_ms = k.total_ms;
   if (launches) *launches = k.launches;
@@ -436,6 +531,36 @@ rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v
     RD_REQUIRE(!(hflags & BAD_RANGE), "node id out of range [0, n)");
     RD_REQUIRE(!(hflags & BAD_LOOP), "self-loop in the edge list");
     RD_REQUIRE(!(hflags & BAD_WEIGHT), "edge weights must be finite and > 0");
+
+    if (flags & RD_REORDER) {
+      // internal ids by decreasing degree (ties by id): the most gathered
+      // entries of a vector share cache lines
+      int32_t *cnt = (int32_t *)dev_alloc((size_t)n * sizeof(int32_t));
+      owned.push_back(cnt);
+      RD_HIP(hipMemset(cnt, 0, (size_t)n * sizeof(int32_t)));
+      hipLaunchKernelGGL(k_count_degree, dim3(grid_for(m, 256)), dim3(256), 0, 0, m, du, dv, cnt);
+      uint32_t *dk = (uint32_t *)dev_alloc(2 * (size_t)n * sizeof(uint32_t));
+      owned.push_back(dk);
+      int32_t *ids = (int32_t *)dev_alloc(2 * (size_t)n * sizeof(int32_t));
+      owned.push_back(ids);
+      hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n, 256)), dim3(256), 0, 0, n, cnt, dk, ids);
+      size_t tb = 0;
+      RD_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, dk, dk + n, ids, ids + n, n, 0, 32,
+                                                (hipStream_t)0));
+      void *tmp0 = dev_alloc(tb);
+      owned.push_back(tmp0);
+      RD_HIP(hipcub::DeviceRadixSort::SortPairs(tmp0, tb, dk, dk + n, ids, ids + n, n, 0, 32,
+                                                (hipStream_t)0));
+      g->perm = (int32_t *)dev_alloc((size_t)n * sizeof(int32_t));
+      hipLaunchKernelGGL(k_rank_of, dim3(grid_for(n, 256)), dim3(256), 0, 0, n,
+                         (const int32_t *)(ids + n), g->perm);
+      hipLaunchKernelGGL(k_relabel_keys, dim3(grid_for(g->nnz, 256)), dim3(256), 0, 0, g->nnz,
+                         (const int32_t *)g->perm, keys);
+      RD_HIP(hipGetLastError());
+      g->perm_host.resize(n);
+      RD_HIP(hipMemcpy(g->perm_host.data(), g->perm, (size_t)n * sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+    }
 
     // sort the 2m directed entries by (row, column); values carry the edge id
     int end_bit = 32;

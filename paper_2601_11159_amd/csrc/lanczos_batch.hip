@@ -489,58 +489,83 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
   block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
 }
 
+// Sum over the LPR lanes of a row segment (result in every lane of it).
+template <int LPR>
+__device__ __forceinline__ double segment_sum(double x) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 // Edge gradient for the pairs held in the columns of X (the accumulated
 // potentials in the scaled basis: phi_p = sqrt(c_p) X[:, p]):
-//   gacc[e] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair,
-// for every undirected edge e = (u, v), visited once from its smaller end.
-// One wavefront per row; lanes over columns; FP64 sums.
-template <typename VT, int B>
+//   gacc[e] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair.
+// One row segment (LPR lanes over the columns) per edge chunk; four edges in
+// flight per segment; FP64 sums in a fixed order.
+template <int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
-    int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const double *__restrict__ X, const double *__restrict__ cw,
     double *__restrict__ gacc) {
-  constexpr int VEC = B >= 64 ? B / 64 : 1;
-  using V = VecN<VT, VEC>;
-  const int lane = threadIdx.x & 63;
-  const int c0 = lane * VEC;
-  const bool on = c0 < B;
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  using XV = VecN<double, VEC>;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, cl = lane % S::LPR, c0 = cl * VEC;
   double w[VEC];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) w[v] = on ? cw[c0 + v] : 0.0;
-  const int gw = blockIdx.x * (SHORT_THREADS / 64) + (threadIdx.x >> 6);
+  for (int v = 0; v < VEC; ++v) w[v] = cw[c0 + v];
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
-  for (int32_t u = gw; u < n; u += nwv) {
-    VecN<double, VEC> xu;
-    if (on) xu = vload<double, VEC>(X + (size_t)u * B + c0);
-    const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
-    for (int32_t p = pb; p < pe; ++p) {
-      const int32_t v = col[p];
-      if (v <= u) continue;  // each edge once, from its smaller end
-      double s = 0.0;
-      if (on) {
-        const VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)v * B + c0);
+  for (int32_t ic = gw * S::RPW + sub; ic < nch; ic += nwv * S::RPW) {
+    const int4 ch = chunk[ic];
+    const int32_t u = ch.x, pe = ch.z;
+    const XV xu = vload<double, VEC>(X + (size_t)u * B + c0);
+    int32_t p = ch.y;
+    for (; p + 4 <= pe; p += 4) {
+      XV xv[4];
 #pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-          const double d = xu.v[k] - xv.v[k];
-          s += w[k] * d * d;
+      for (int k = 0; k < 4; ++k) xv[k] = vload<double, VEC>(X + (size_t)col[p + k] * B + c0);
+      double sk[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double d = xu.v[v] - xv[k].v[v];
+          a += w[v] * d * d;
         }
+        sk[k] = segment_sum<S::LPR>(a);
       }
-      s = wave_sum(s);
-      if (lane == 0) gacc[eid[p]] -= s;
+      if (cl < 4) {
+        const double mine = cl == 0 ? sk[0] : cl == 1 ? sk[1] : cl == 2 ? sk[2] : sk[3];
+        gacc[eid[p + cl]] -= mine;
+      }
+    }
+    for (; p < pe; ++p) {
+      const XV xv = vload<double, VEC>(X + (size_t)col[p] * B + c0);
+      double a = 0.0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const double d = xu.v[v] - xv.v[v];
+        a += w[v] * d * d;
+      }
+      a = segment_sum<S::LPR>(a);
+      if (cl == 0) gacc[eid[p]] -= a;
     }
   }
 }
 
 // Per-column energy of the accumulated potentials, sum_e w_e (X[u,p] - X[v,p])^2
-// in FP64, as per-block column partials (each edge once, from its smaller end).
-template <typename VT, int B, bool WEIGHTED>
+// in FP64, as per-block column partials (edge chunks as in k_grad_edges).
+template <int B, bool WEIGHTED>
 __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
-    int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
     const double *__restrict__ w64, const double *__restrict__ X, double *__restrict__ part,
     int32_t ldp) {
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
-  using V = VecN<VT, VEC>;
+  using XV = VecN<double, VEC>;
   __shared__ double sm[(SHORT_THREADS / 64) * B];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
@@ -549,18 +574,32 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
   for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
-  for (int32_t u = gw * S::RPW + sub; u < n; u += nwv * S::RPW) {
-    const VecN<double, VEC> xu = vload<double, VEC>(X + (size_t)u * B + c0);
-    const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
-    for (int32_t p = pb; p < pe; ++p) {
-      const int32_t v = col[p];
-      if (v <= u) continue;
-      const VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)v * B + c0);
+  for (int32_t ic = gw * S::RPW + sub; ic < nch; ic += nwv * S::RPW) {
+    const int4 ch = chunk[ic];
+    const int32_t u = ch.x, pe = ch.z;
+    const XV xu = vload<double, VEC>(X + (size_t)u * B + c0);
+    int32_t p = ch.y;
+    for (; p + 4 <= pe; p += 4) {
+      XV xv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xv[k] = vload<double, VEC>(X + (size_t)col[p + k] * B + c0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double we = WEIGHTED ? w64[p + k] : 1.0;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double d = xu.v[v] - xv[k].v[v];
+          acc[v] += we * d * d;
+        }
+      }
+    }
+    for (; p < pe; ++p) {
+      const XV xv = vload<double, VEC>(X + (size_t)col[p] * B + c0);
       const double we = WEIGHTED ? w64[p] : 1.0;
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        const double d = xu.v[k] - xv.v[k];
-        acc[k] += we * d * d;
+      for (int v = 0; v < VEC; ++v) {
+        const double d = xu.v[v] - xv.v[v];
+        acc[v] += we * d * d;
       }
     }
   }
@@ -706,6 +745,16 @@ __global__ void k_check_pairs(int32_t npairs, int32_t n, const int32_t *__restri
                               const int32_t *__restrict__ t, int32_t *__restrict__ flag) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < npairs && (s[i] < 0 || s[i] >= n || t[i] < 0 || t[i] >= n)) atomicOr(flag, 1);
+}
+
+// caller ids -> internal ids of a reordered graph
+__global__ void k_map_pairs(int32_t npairs, const int32_t *__restrict__ perm,
+                            const int32_t *__restrict__ s, const int32_t *__restrict__ t,
+                            int32_t *__restrict__ ms, int32_t *__restrict__ mt) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  ms[i] = perm[s[i]];
+  mt[i] = perm[t[i]];
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -982,6 +1031,7 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
   if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
   if (!refine) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
+  edge_chunks(g, st);
   for (int32_t off = 0; off < npairs; off += B) {
     const int32_t nb = std::min<int32_t>(B, npairs - off);
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
@@ -991,13 +1041,13 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
     if (refine) {
       if (g->unit)
-        hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->n, g->row_ptr, g->col, (const double *)nullptr, (const double *)bw->Xp,
-                           bw->part, bw->ldp);
+        hipLaunchKernelGGL((k_energy<B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                           g->nch, (const int4 *)g->echunk, g->col, (const double *)nullptr,
+                           (const double *)bw->Xp, bw->part, bw->ldp);
       else
-        hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->n, g->row_ptr, g->col, (const double *)g->w64, (const double *)bw->Xp,
-                           bw->part, bw->ldp);
+        hipLaunchKernelGGL((k_energy<B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                           g->nch, (const int4 *)g->echunk, g->col, (const double *)g->w64,
+                           (const double *)bw->Xp, bw->part, bw->ldp);
       hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                          bw->cw, bw->qstate + 3);
       hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
@@ -1005,9 +1055,21 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     } else {
       hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
                          grad_r ? grad_r + off : nullptr, bw->cw);
-      hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                         g->row_ptr, g->col, g->eid, (const double *)bw->Xp, (const double *)bw->cw,
-                         bw->gacc);
+      std::pair<hipEvent_t, hipEvent_t> ev{};
+      if (prof) {
+        ev = g->timer[2].next();
+        RD_HIP(hipEventRecord(ev.first, st));
+      }
+      hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                         (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xp,
+                         (const double *)bw->cw, bw->gacc);
+      if (prof) {
+        RD_HIP(hipEventRecord(ev.second, st));
+        // chunks, column and edge ids of the upper entries, the accumulator
+        // read and written, the potential block read once
+        g->timer[2].alg_bytes = 16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
+                                8.0 * B * (double)g->n + 8.0 * B;
+      }
     }
     RD_HIP(hipGetLastError());
   }
@@ -1015,6 +1077,10 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
                        (const double *)bw->gacc, grad_w);
     RD_HIP(hipGetLastError());
+    if (prof) {
+      RD_HIP(hipStreamSynchronize(st));
+      g->timer[2].resolve(g->timer[2].used);
+    }
   }
 }
 
@@ -1149,6 +1215,15 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
     RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     RD_HIP(hipStreamSynchronize(st));
     RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+    if (g->perm) {
+      int32_t *mp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(mp);
+      hipLaunchKernelGGL(k_map_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->perm, ds,
+                         dt, mp, mp + npairs);
+      RD_HIP(hipGetLastError());
+      ds = mp;
+      dt = mp + npairs;
+    }
     int32_t B = opt.block_width;
     RD_REQUIRE(B == 0 || B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
@@ -1236,6 +1311,14 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
       RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       RD_HIP(hipStreamSynchronize(st));
       RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+      if (g->perm) {
+        int32_t *mp = (int32_t *)tmp(2 * (size_t)npairs * sizeof(int32_t));
+        hipLaunchKernelGGL(k_map_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->perm,
+                           ds, dt, mp, mp + npairs);
+        RD_HIP(hipGetLastError());
+        ds = mp;
+        dt = mp + npairs;
+      }
     }
     int32_t B = opt.block_width;
     if (B == 0) B = autotune_width(g, bw, opt.precision, std::max(npairs, 1), st);

@@ -387,6 +387,10 @@ rd_status rd_query(rd_graph g, int32_t s, int32_t t, double eps, const rd_option
       return RD_OK;
     }
     RD_HIP(hipSetDevice(g->device));
+    if (g->perm) {
+      s = g->perm_host[s];
+      t = g->perm_host[t];
+    }
     plain_run(g, s, t, eps, opt, pick_stream(g, o), out, nullptr, nullptr, nullptr, 0);
     return RD_OK;
   } catch (const RdError &e) {
@@ -405,6 +409,10 @@ rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
     RD_REQUIRE(s >= 0 && s < g->n && t >= 0 && t < g->n && s != t, "need s != t in [0, n)");
     opt.fixed_k = k;
     RD_HIP(hipSetDevice(g->device));
+    if (g->perm) {
+      s = g->perm_host[s];
+      t = g->perm_host[t];
+    }
     hipStream_t st = pick_stream(g, o);
     dtr = (double *)dev_alloc(3 * (size_t)k * sizeof(double));
     RD_HIP(hipMemsetAsync(dtr, 0, 3 * (size_t)k * sizeof(double), st));

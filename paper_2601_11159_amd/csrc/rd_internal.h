@@ -106,7 +106,16 @@ struct rd_graph_s {
   int32_t *blk_row = nullptr;  // [nblk+1] first row of each block
   int8_t *blk_lanes = nullptr; // [nblk] log2(lanes per row) for multi-row blocks, -1 for one long row
 
-  KernelTimer timer[2];  // 0: batched short-row product, 1: single-pair product
+  // edge-pass work items (built on first use): the entries (u, v > u) of
+  // each row cut into chunks of at most EDGE_CHUNK, as (u, begin, end, 0)
+  int32_t nch = 0;
+  int4 *echunk = nullptr;
+
+  // RD_REORDER: internal id of every caller id (nullptr: identity)
+  int32_t *perm = nullptr;
+  std::vector<int32_t> perm_host;
+
+  KernelTimer timer[3];  // 0: batched short-row product, 1: single-pair product, 2: edge gradient
   PlainWork *plain = nullptr;
   BatchWork *batch = nullptr;
 
@@ -121,6 +130,13 @@ void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 hipStream_t pick_stream(rd_graph g, const rd_options *o);
 rd_options resolve_options(rd_graph g, const rd_options *o);
+
+// Work items of the edge passes (gradient, energy): every undirected edge once,
+// as the adjacency entry (u, v) with v > u. Columns ascend within a row, so
+// these entries are a suffix of row u; the suffix is cut into chunks of at most
+// EDGE_CHUNK entries so that the edges of a hub row spread over many wavefronts.
+constexpr int EDGE_CHUNK = 32;
+void edge_chunks(rd_graph g, hipStream_t st);
 
 // plain single-pair path (lanczos_plain.hip)
 void plain_free(rd_graph g);

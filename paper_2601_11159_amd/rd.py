@@ -29,6 +29,7 @@ RD_E_BREAKDOWN = 6
 RD_DEVICE_PTRS = 0x1
 RD_PROFILE = 0x2
 RD_GENERAL_PATH = 0x4
+RD_REORDER = 0x8
 RD_F64 = 0
 RD_F32 = 1
 
@@ -158,7 +159,9 @@ def _stream_of(opts: Optional[RdOptions], device: bool = False) -> RdOptions:
 class RDGraph:
     """Owning wrapper of an rd_graph handle."""
 
-    def __init__(self, n: int, u, v, w=None):
+    def __init__(self, n: int, u, v, w=None, reorder: bool = False):
+        """reorder: number the nodes internally by decreasing degree (RD_REORDER);
+        node ids, pair lists and edge order seen by the caller do not change."""
         lib = load()
         m = int(len(u))
         pu, du, ku = _ptr(u, np.int32, m)
@@ -173,7 +176,7 @@ class RDGraph:
             pw, dw, kw_ = _ptr(w, np.float32 if is32 else np.float64, m)
         if not (du == dv == dw):
             raise ValueError("edge arrays and weights must all be host or all be device memory")
-        flags = RD_DEVICE_PTRS if du else 0
+        flags = (RD_DEVICE_PTRS if du else 0) | (RD_REORDER if reorder else 0)
         h = ctypes.c_void_p()
         rc = lib.rd_init_graph(int(n), m, pu, pv, pw, wdt, flags, ctypes.byref(h))
         if rc != RD_OK:
@@ -226,7 +229,8 @@ class RDGraph:
     def kernel_stats(self, which: int):
         """(total ms, launches, algorithmic bytes per launch) of the sparse
         product launches timed under RD_PROFILE since the last call.
-        which = 0: batched short-row product; 1: single-pair product."""
+        which = 0: batched short-row product; 1: single-pair product;
+        2: edge pass of grad_edges."""
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         rc = load().rd_kernel_stats(self._h, int(which), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
         if rc != RD_OK:

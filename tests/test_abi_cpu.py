@@ -27,6 +27,14 @@ def test_library_exports_every_declared_symbol():
     assert sorted(rd.EXPORTED) == declared
 
 
+def test_header_constants_match_binding():
+    txt = open(os.path.join(ROOT, "include", "rd.h")).read()
+    defs = dict(re.findall(r"#define (RD_[A-Z0-9_]+) (0x[0-9a-f]+|\d+)u?", txt))
+    assert set(defs) >= {"RD_DEVICE_PTRS", "RD_PROFILE", "RD_GENERAL_PATH", "RD_REORDER", "RD_F64", "RD_F32"}
+    for name, val in defs.items():
+        assert getattr(rd, name) == int(val, 0), name
+
+
 def test_status_strings_without_gpu():
     assert rd.rd_status_string(rd.RD_OK) == "ok"
     assert "connected" in rd.rd_status_string(rd.RD_E_NOT_CONNECTED)

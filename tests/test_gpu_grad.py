@@ -146,3 +146,36 @@ def test_autograd_function_matches_dense():
     r32.sum().backward()
     assert w32.grad.dtype == torch.float32
     assert torch.isfinite(w32.grad).all()
+
+
+def _hub_graph():
+    # node 0 joined to every other node: its row holds ~1000 upper entries,
+    # cut into many edge chunks with a ragged last one
+    rng = np.random.default_rng(41)
+    n = 1003
+    edges = {(0, i) for i in range(1, n)}
+    while len(edges) < n - 1 + 2500:
+        a, b = (int(x) for x in rng.integers(1, n, size=2))
+        if a != b:
+            edges.add((min(a, b), max(a, b)))
+    pairs = sorted(edges)
+    return I._canon(n, pairs, rng.uniform(0.25, 4.0, size=len(pairs)), "hub_1003")
+
+
+@pytest.mark.parametrize("width", [16, 32, 64, 128, 256])
+def test_gradient_and_refinement_on_hub_rows(width):
+    g = _hub_graph()
+    s, t = I.uniform_pairs(g.n, 50, seed=42)
+    s[0], t[0] = 0, 7  # the hub itself
+    t[5] = s[5]
+    Lp = D.pinv(D.laplacian(g))
+    ref = D.grad_edges(g, Lp, s, t)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    fwd, gw = G.grad_edges(s, t, None, 1e-12, _opts(block_width=width))
+    assert np.linalg.norm(gw - ref) / np.linalg.norm(ref) <= 1e-6
+    assert np.max(np.abs(gw - ref)) <= 1e-6 * np.max(np.abs(ref))
+    mask = s != t
+    truth = D.rd_from_pinv(Lp, s[mask], t[mask])
+    out = G.query_batch(s, t, 1e-10, _opts(block_width=width, refine=1))
+    assert out["r"][5] == 0.0
+    np.testing.assert_allclose(out["r"][mask], truth, rtol=1e-9)
