@@ -629,7 +629,7 @@ rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v
 
     std::vector<int32_t> rp(n + 1);
     RD_HIP(hipMemcpy(rp.data(), g->row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    build_row_blocks(g, rp, 2048, 1024);  // must match the SpMV's LDS staging limits
+    build_row_blocks(g, rp, SPMV_BLOCK_NNZ, SPMV_BLOCK_ROWS);
 
     for (void *p : owned) dev_free(p);
     owned.clear();

@@ -16,6 +16,9 @@
 //   k_reduce_alpha  alpha_i, LDL^T update of I - T_i, r_hat_i, stopping test
 //   k_update        w = y - alpha_i q_i                       (+ per-block ||w||_D^2)
 //   k_reduce_beta   beta_{i+1}, breakdown test, next scales
+// (The partial sums are combined by separate one-block launches: a last-block
+// reduction inside the producing kernel needs a device-scope release per block,
+// which writes back the whole L2 of its XCD and made the product 6x slower.)
 // Every kernel returns at once when the run has stopped, so the host may
 // enqueue iterations ahead of the stopping decision.
 
@@ -27,8 +30,10 @@
 namespace {
 
 constexpr int SPMV_THREADS = 256;
-constexpr int BLOCK_NNZ = 2048;   // adjacency entries staged per multi-row block
-constexpr int BLOCK_ROWS = 1024;  // rows per multi-row block (the schedule guarantees it)
+constexpr int BLOCK_NNZ = SPMV_BLOCK_NNZ;    // adjacency entries staged per multi-row block
+constexpr int BLOCK_ROWS = SPMV_BLOCK_ROWS;  // rows per multi-row block (the schedule guarantees it)
+static_assert(BLOCK_ROWS == SPMV_THREADS, "one epilogue row per thread");
+static_assert(BLOCK_NNZ % SPMV_THREADS == 0, "whole gather rounds");
 constexpr int UPD_THREADS = 256;
 constexpr int RED_THREADS = 1024;
 
@@ -44,6 +49,13 @@ struct VecTraits<float> {
   static const float *w(rd_graph g) { return g->w32; }
   static const float *invdeg(rd_graph g) { return g->invdeg32; }
 };
+
+// Fixed-order sum of nb partials by one block.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb, double *sm) {
+  double a = 0.0;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) a += part[j];
+  return block_sum(a, sm);
+}
 
 // y_u = sig (1/d_u) sum_v w_uv U_cur[v] - prev_coef U_prev[u], written over
 // U_prev[u]; per-block partial of sum_u d_u y_u (sig U_cur[u]).
@@ -75,26 +87,60 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
   double apart = 0.0;
   if (lg < 0) {
     const int32_t p0 = row_ptr[r0], p1 = row_ptr[r0 + 1];
-    VT acc = 0;
-    for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
-      VT x = Ucur[col[p]];
-      acc += WEIGHTED ? w[p] * x : x;
+    VT acc[4] = {0, 0, 0, 0};
+    int32_t p = p0 + tid;
+    for (; p + 3 * SPMV_THREADS < p1; p += 4 * SPMV_THREADS) {
+      int32_t c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = col[p + k * SPMV_THREADS];
+      VT x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = Ucur[c[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += WEIGHTED ? w[p + k * SPMV_THREADS] * x[k] : x[k];
     }
-    acc = block_sum(acc, vred);
+    for (; p < p1; p += SPMV_THREADS) {
+      const VT x = Ucur[col[p]];
+      acc[0] += WEIGHTED ? w[p] * x : x;
+    }
+    VT a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    a = block_sum(a, vred);
     if (tid == 0) {
-      VT y = sig * acc * invdeg[r0];
+      VT y = sig * a * invdeg[r0];
       if (has_prev) y -= pc * Y[r0];
       Y[r0] = y;
       apart = deg[r0] * (double)y * ((double)sig * (double)Ucur[r0]);
     }
   } else {
     const int32_t nrows = r1 - r0;
+    const int32_t p0 = row_ptr[r0], p1 = row_ptr[r1];
     for (int32_t j = tid; j <= nrows; j += SPMV_THREADS) rp[j] = row_ptr[r0 + j];
-    __syncthreads();
-    const int32_t p0 = rp[0], p1 = rp[nrows];
-    for (int32_t p = p0 + tid; p < p1; p += SPMV_THREADS) {
-      VT x = Ucur[col[p]];
-      vals[p - p0] = WEIGHTED ? w[p] * x : x;
+    // operands of this thread's epilogue row, loaded while the products are gathered
+    const bool mine = tid < nrows;
+    const int32_t r = r0 + tid;
+    VT e_id = 0, e_u = 0, e_y = 0;
+    double e_d = 0.0;
+    if (mine) {
+      e_id = invdeg[r];
+      e_u = Ucur[r];
+      e_d = deg[r];
+      if (has_prev) e_y = Y[r];
+    }
+    // at most BLOCK_NNZ entries: every index load, then every gather, in flight at once
+    constexpr int PER = BLOCK_NNZ / SPMV_THREADS;
+    int32_t c[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int32_t p = p0 + tid + k * SPMV_THREADS;
+      c[k] = p < p1 ? col[p] : -1;
+    }
+    VT x[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) x[k] = c[k] >= 0 ? Ucur[c[k]] : VT(0);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int32_t p = p0 + tid + k * SPMV_THREADS;
+      if (p < p1) vals[p - p0] = WEIGHTED ? w[p] * x[k] : x[k];
     }
     __syncthreads();
     const int gsz = 1 << lg, lane = tid & (gsz - 1);
@@ -107,25 +153,19 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
       if (lane == 0) rsum[j] = acc;
     }
     __syncthreads();
-    for (int32_t j = tid; j < nrows; j += SPMV_THREADS) {
-      const int32_t r = r0 + j;
-      VT y = sig * rsum[j] * invdeg[r];
-      if (has_prev) y -= pc * Y[r];
+    if (mine) {
+      VT y = sig * rsum[tid] * e_id;
+      if (has_prev) y -= pc * e_y;
       Y[r] = y;
-      apart += deg[r] * (double)y * ((double)sig * (double)Ucur[r]);
+      apart = e_d * (double)y * ((double)sig * (double)e_u);
     }
   }
   apart = block_sum(apart, red);
   if (tid == 0) part[b] = apart;
 }
 
-// Fixed-order sum of nb partials by one block.
-__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb, double *sm) {
-  double a = 0.0;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) a += part[j];
-  return block_sum(a, sm);
-}
-
+// alpha_i from the product's partials (fixed order), the LDL^T update of
+// I - T_i, r_hat_i and the stopping test.
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_alpha(const double *__restrict__ part, int nb,
                                                               LzState *__restrict__ st,
                                                               double *tr_alpha, double *tr_rhat) {
@@ -138,6 +178,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_alpha(const double *__re
     *st = S;
   }
 }
+
 
 // w = y - alpha_i sig_i U_cur, in place over y; per-block partial of sum d w^2.
 template <typename VT>
@@ -158,6 +199,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(int32_t n, const double 
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// beta_{i+1} (fixed order), breakdown test, next scales.
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(const double *__restrict__ part, int nb,
                                                              LzState *__restrict__ st,
                                                              double *tr_beta) {

@@ -131,6 +131,11 @@ void dev_free(void *p);
 hipStream_t pick_stream(rd_graph g, const rd_options *o);
 rd_options resolve_options(rd_graph g, const rd_options *o);
 
+// Row blocks of the single-pair product: at most SPMV_BLOCK_NNZ adjacency
+// entries and SPMV_BLOCK_ROWS rows each (a longer row is a block of its own).
+constexpr int SPMV_BLOCK_NNZ = 1024;
+constexpr int SPMV_BLOCK_ROWS = 256;
+
 // Work items of the edge passes (gradient, energy): every undirected edge once,
 // as the adjacency entry (u, v) with v > u. Columns ascend within a row, so
 // these entries are a suffix of row u; the suffix is cut into chunks of at most
