@@ -82,6 +82,7 @@ def _plain_rate(G, rd, s, t, eps, opts):
 def _batch_rate(G, rd, s, t, eps, opts, steps=1):
     import torch
     G.query_batch(s[: min(len(s), 64)], t[: min(len(s), 64)], eps, opts)
+    log("  warm-up done")
     G.kernel_stats(0)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -170,14 +171,22 @@ def run_other(name, args):
         G = rd.RDGraph(g.n, g.u, g.v)
         ref = np.array([G.query(int(s[p]), int(t[p]), 1e-10, rd.rd_default_options(max_iters=100000)).r
                         for p in range(8)])
+        log("reference values at eps 1e-10 done")
         npl = 8
         plain_qps, pr, pit, proof, pdt = _plain_rate(G, rd, s[:npl], t[:npl], 1e-4,
                                                      rd.rd_default_options(flags=rd.RD_PROFILE, max_iters=100000))
         o32 = rd.rd_default_options(precision=rd.RD_F32, refine=1, block_width=64, max_iters=100000,
                                     flags=rd.RD_PROFILE)
+        log(f"plain FP64: {plain_qps:.3f} q/s")
         bq, bout, broof, bdt = _batch_rate(G, rd, s, t, 1e-5, o32)
+        log(f"batched FP32 refined: {bq:.3f} q/s")
         raw = G.query_batch(s[:64], t[:64], 1e-4, rd.rd_default_options(precision=rd.RD_F32, block_width=64,
                                                                          max_iters=100000))
+        # batched FP64 (no refinement) on all pairs at the 1e-4 target
+        log("batched FP32 unrefined (64 pairs) done")
+        o64 = rd.rd_default_options(precision=rd.RD_F64, block_width=64, max_iters=100000, flags=rd.RD_PROFILE)
+        b64q, b64out, b64roof, b64dt = _batch_rate(G, rd, s, t, 1e-4, o64)
+        log(f"batched FP64: {b64q:.3f} q/s")
         # CPU oracle: a bounded number of iterations of one pair, scaled to a query
         from threadpoolctl import threadpool_limits
         from oracle import lanczos as LZ
@@ -186,14 +195,20 @@ def run_other(name, args):
             t1 = time.time()
             LZ.lanczos_rd(g, int(s[0]), int(t[0]), k=300, A=A, d=d)
             per_it = (time.time() - t1) / 300
-        line = _line("queries/s", bq, 1, 1, bdt * 1e3, "f32",
-                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256,
-                      "path": "batched FP32 sparse products + FP64 scalars + FP64 energy refinement, eps 1e-5 "
-                              "for the 1e-4 target (value); plain FP64 at 1e-4 on 8 pairs beside it"},
+        # value: the fastest path that meets 1e-4 here (batched FP64); the FP32
+        # path stops at ~1.2e-4 on this graph even with the FP64 energy refinement
+        line = _line("queries/s", b64q, 1, 1, b64dt * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": 1e-4,
+                      "path": "batched FP64 at eps 1e-4, width 64 (value); plain FP64 at 1e-4 on 8 pairs and "
+                              "batched FP32 + FP64 energy refinement at eps 1e-5 beside it"},
                      plain_fp64={"value": round(plain_qps, 3), "unit": "queries/s", "mean_iters": float(pit.mean()),
                                  "roofline": proof},
-                     speedup_batched_vs_plain_fp64=round(bq / plain_qps, 2),
-                     roofline=dict(broof, note="FP32 block of 4M x 64 per vector; refinement adds two vector streams"),
+                     speedup_batched_fp64_vs_plain_fp64=round(b64q / plain_qps, 2),
+                     batched_fp32_refined={"value": round(bq, 3), "unit": "queries/s", "eps_rel": 1e-5,
+                                           "max_rel_err": float(np.max(np.abs(bout['r'][:8] - ref) / ref)),
+                                           "roofline": dict(broof, note="refinement adds two FP64 vector streams"),
+                                           "speedup_vs_plain_fp64": round(bq / plain_qps, 2)},
+                     roofline=b64roof,
                      cpu_baseline={"value": round(1.0 / (per_it * float(pit.mean())), 6), "unit": "queries/s",
                                    "cores": 1, "kind": "oracle",
                                    "sample": f"300 iterations of numpy Algorithm 3 on one pair ({per_it * 300:.1f}s), "
@@ -202,6 +217,7 @@ def run_other(name, args):
                                           "road-like grids is tested at 300x300)",
                              "batched_fp32_refined_max_rel_err": float(np.max(np.abs(bout['r'][:8] - ref) / ref)),
                              "batched_fp32_unrefined_max_rel_err": float(np.max(np.abs(raw['r'][:8] - ref) / ref)),
+                             "batched_fp64_max_rel_err": float(np.max(np.abs(b64out['r'][:8] - ref) / ref)),
                              "plain_fp64_max_rel_err": float(np.max(np.abs(pr - ref) / ref))})
     elif name == "weighted_chung_lu_n1M_grad_256pairs":
         g = I.chung_lu(1_000_000, 2.1, 20.0, 2)

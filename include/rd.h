@@ -72,7 +72,7 @@ typedef struct {
                           RD_F32: vectors and sparse products in FP32 with FP32
                           accumulation; inner products summed in FP64; the
                           Lanczos scalars and the tridiagonal solve in FP64. */
-  int32_t max_iters;   /* iteration cap; 0 = min(n, 100000) */
+  int32_t max_iters;   /* iteration cap; 0 = max(fixed_k, min(n, 100000)) */
   int32_t fixed_k;     /* > 0: run exactly k iterations, as Algorithm 3 states
                           it (eps is ignored; an exact breakdown still stops) */
   int32_t delay;       /* window d of the stopping estimator; 0 = 8 */
@@ -89,6 +89,18 @@ typedef struct {
                           the squared energy-norm error of phi, so rounding in
                           FP32 vectors enters only to second order. Pairs run
                           in groups of block_width without refill. */
+  int32_t reorth;      /* re-orthogonalisation of w after w -= alpha_i v_i
+                          (not in Algorithm 3, which relies on v_1 being
+                          exactly orthogonal to u_1 = D^{1/2} 1 / sqrt(vol),
+                          the eigenvector of calA for eigenvalue 1), with FP64
+                          coefficients all taken from that w:
+                          0: none (the paper's loop);
+                          1: w -= (u_1^T w) u_1;
+                          2: also w -= (v_i^T w) v_i + (v_{i-1}^T w) v_{i-1}.
+                          From the second iteration on (v_1 is orthogonal to
+                          u_1 by construction). Costs one more vector pass
+                          per iteration; graphs small enough for the
+                          single-workgroup path take the general path. */
   void *stream;        /* hipStream_t, NULL = the handle's stream */
 } rd_options;
 

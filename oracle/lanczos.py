@@ -24,6 +24,14 @@ after each iteration on the sequence r_hat_1, r_hat_2, ...
 
 Exact breakdown (beta_{i+1} = 0, the Krylov space is invariant) ends the run
 with r_hat exact; the test is beta_{i+1} <= 1e-13 (|alpha_i| + beta_i).
+
+Optional re-orthogonalisation (`reorth`, not part of Algorithm 3; the paper
+relies on v_1 being exactly orthogonal to u_1 = D^{1/2} 1 / sqrt(vol), the
+eigenvector of calA for eigenvalue 1, Section 3): after w = w - alpha_i v_i,
+with coefficients all taken from that w (one classical Gram-Schmidt step),
+  reorth = 1: w -= (u_1^T w) u_1;
+  reorth = 2: w -= (u_1^T w) u_1 + (v_i^T w) v_i + (v_{i-1}^T w) v_{i-1}.
+In exact arithmetic every coefficient is zero and the run is unchanged.
 """
 
 from __future__ import annotations
@@ -121,9 +129,11 @@ class LanczosRun:
 
 
 def lanczos_rd(g, s: int, t: int, k: int | None = None, tol: float | None = None, delay: int = 8,
-               max_iters: int | None = None, keep_vectors: bool = False, A=None, d=None) -> LanczosRun:
+               max_iters: int | None = None, keep_vectors: bool = False, A=None, d=None,
+               reorth: int = 0) -> LanczosRun:
     """Algorithm 3 for the pair (s, t): fixed k iterations when `k` is given,
-    otherwise iterate until `stop_rule(tol, delay)` holds or `max_iters`."""
+    otherwise iterate until `stop_rule(tol, delay)` holds or `max_iters`.
+    `reorth` in {0, 1, 2} as in the module docstring."""
     if A is None:
         A, d = normalized_adjacency(g)
     if s == t:
@@ -136,6 +146,7 @@ def lanczos_rd(g, s: int, t: int, k: int | None = None, tol: float | None = None
     v[t] = -1.0 / np.sqrt(d[t])
     v /= np.sqrt(c)
     beta_i = 0.0
+    u1 = np.sqrt(d) / np.sqrt(d.sum())
     run = LanczosRun(r=0.0, k=0, beta=[0.0])
     limit = k if k is not None else (max_iters if max_iters is not None else n)
     for i in range(1, limit + 1):
@@ -144,6 +155,11 @@ def lanczos_rd(g, s: int, t: int, k: int | None = None, tol: float | None = None
         w = A @ v - beta_i * v_prev
         alpha_i = float(w @ v)
         w = w - alpha_i * v
+        if reorth >= 1:
+            corr = (u1 @ w) * u1
+            if reorth == 2:
+                corr = corr + (v @ w) * v + (v_prev @ w) * v_prev
+            w = w - corr
         beta_next = float(np.linalg.norm(w))
         run.alpha.append(alpha_i)
         run.beta.append(beta_next)

@@ -216,6 +216,15 @@ const T *to_device(const T *p, int64_t count, bool device_ptrs, std::vector<void
   return d;
 }
 
+// vol = sum_u d_u in FP64, summed on the host in node order.
+static void compute_volume(rd_graph g) {
+  std::vector<double> d(g->n);
+  RD_HIP(hipMemcpy(d.data(), g->deg, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost));
+  double v = 0.0;
+  for (double x : d) v += x;
+  g->vol = v;
+}
+
 void set_weights_impl(rd_graph g, const void *w, int32_t w_dtype, uint32_t flags) {
   RD_REQUIRE(w_dtype == RD_F64 || w_dtype == RD_F32, "w_dtype must be RD_F64 or RD_F32");
   std::vector<void *> owned;
@@ -245,6 +254,7 @@ void set_weights_impl(rd_graph g, const void *w, int32_t w_dtype, uint32_t flags
     RD_HIP(hipGetLastError());
     RD_HIP(hipDeviceSynchronize());
     g->unit = false;
+    compute_volume(g);
     for (void *p : owned) dev_free(p);
     owned.clear();
   } catch (...) {
@@ -294,12 +304,13 @@ rd_options resolve_options(rd_graph g, const rd_options *o) {
   if (o) r = *o;
   RD_REQUIRE(r.precision == RD_F64 || r.precision == RD_F32, "precision must be RD_F64 or RD_F32");
   RD_REQUIRE(r.max_iters >= 0 && r.fixed_k >= 0, "max_iters and fixed_k must be >= 0");
-  if (r.max_iters == 0) r.max_iters = std::min<int32_t>(g->n, 100000);
+  if (r.max_iters == 0) r.max_iters = std::max(r.fixed_k, std::min<int32_t>(g->n, 100000));
   if (r.delay == 0) r.delay = 8;
   RD_REQUIRE(r.delay >= 1 && r.delay <= RD_HIST - 2, "delay must be in [1, 14]");
   RD_REQUIRE(r.err_mode == 0 || r.err_mode == 1, "err_mode must be 0 or 1");
   RD_REQUIRE(r.block_width >= 0 && r.block_width <= 256, "block_width must be in [0, 256]");
   RD_REQUIRE(r.refine == 0 || r.refine == 1, "refine must be 0 or 1");
+  RD_REQUIRE(r.reorth >= 0 && r.reorth <= 2, "reorth must be 0, 1 or 2");
   return r;
 }
 
@@ -430,6 +441,7 @@ void rd_default_options(rd_options *o) {
   o->fixed_k = 0;
   o->delay = 8;
   o->refine = 0;
+  o->reorth = 0;
   o->block_width = 0;
   o->err_mode = 0;
   o->flags = 0;
@@ -605,6 +617,7 @@ rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v
     RD_REQUIRE(!(hf[0] & BAD_DUP), "duplicate edge in the edge list");
     if (hf[0] & BAD_ISOLATED) throw RdError{RD_E_NOT_CONNECTED, "graph has an isolated node"};
     g->max_deg = hf[1];
+    compute_volume(g);
 
     // connectivity: level-synchronous BFS from node 0
     {

@@ -50,9 +50,14 @@ struct ColCtrl {
   double vt;
   double pa;    // gradient mode: p_i = q_i + pa p_{i-1}
   double xb;    //                x_i = x_{i-1} + xb p_i
+  double ro_mu;  // re-orthogonalisation: W -= ro_mu + ro_c U_cur + ro_p U_prev
+  double ro_c;
+  double ro_p;
   int32_t mode;  // COL_*
   int32_t s, t;
   int32_t prev_sparse;  // the previous vector is q_1 (vs at s, vt at t, zero elsewhere)
+  int32_t upd_sparse;   // the same, for the update of the current iteration
+  int32_t pad;
 };
 
 template <typename VT, int N>
@@ -77,7 +82,8 @@ struct Shape {
 };
 
 // Fold the per-lane column partials of all rows handled by a block into
-// part[j * ldp + slot] (fixed order: sub-rows of a wave, then waves).
+// part[j * ldp + slot] (fixed order: sub-rows of a wave, then waves). Ends with
+// a barrier, so `sm` may be reused by a following call.
 template <int B, int VEC>
 __device__ __forceinline__ void block_column_partials(double (&apart)[VEC], double *sm, double *part,
                                                       int32_t ldp, int32_t slot) {
@@ -96,6 +102,7 @@ __device__ __forceinline__ void block_column_partials(double (&apart)[VEC], doub
     for (int w = 0; w < nw; ++w) a += sm[w * B + j];
     part[(size_t)j * ldp + slot] = a;
   }
+  __syncthreads();
 }
 
 // Rows of length <= LONG_DEG. Wave work items are contiguous row ranges of
@@ -105,8 +112,8 @@ template <typename VT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
     int32_t nwi, const int32_t *__restrict__ witem_row, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
-    const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
-    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp,
+    const double *__restrict__ deg, const VT *__restrict__ Ucur, const VT *__restrict__ Uprev,
+    VT *__restrict__ Y, const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp,
     const int32_t *__restrict__ active) {
   if (*active == 0) return;
   using S = Shape<B>;
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
       }
       const VT id = invdeg[r];
       const double dr = deg[r];
-      const V up = vload<VT, VEC>(Y + (size_t)r * B + c0);
+      const V up = vload<VT, VEC>(Uprev + (size_t)r * B + c0);
       const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
       V y;
 #pragma unroll
@@ -190,9 +197,9 @@ template <typename VT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
     const int32_t *__restrict__ long_rows, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
-    const double *__restrict__ deg, const VT *__restrict__ Ucur, VT *__restrict__ Y,
-    const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp, int32_t poff,
-    const int32_t *__restrict__ active) {
+    const double *__restrict__ deg, const VT *__restrict__ Ucur, const VT *__restrict__ Uprev,
+    VT *__restrict__ Y, const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp,
+    int32_t poff, const int32_t *__restrict__ active) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
     }
     const VT id = invdeg[r];
     const double dr = deg[r];
-    const V up = vload<VT, VEC>(Y + (size_t)r * B + c0);
+    const V up = vload<VT, VEC>(Uprev + (size_t)r * B + c0);
     const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
     V y;
 #pragma unroll
@@ -283,6 +290,7 @@ struct RunParams {
   double tol;
   int32_t max_iters, fixed_k, delay, err_mode;
   int32_t npairs;
+  int32_t reorth;
 };
 
 __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
@@ -370,6 +378,7 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       cc.vs = rc / deg[s];
       cc.vt = -rc / deg[t];
       cc.prev_sparse = 0;
+      cc.upd_sparse = 0;
       cc.s = s;
       cc.t = t;
       active = 1;
@@ -384,10 +393,12 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       if (final_term) active = 1;
       cc.pc = 0.0;
       cc.coef = 0.0;
+      cc.upd_sparse = 0;
       if (!final_term) cc.sig = 0.0;
     } else {
       cc.mode = COL_RUN;
       cc.coef = S.alpha * S.sig_cur;
+      cc.upd_sparse = cc.prev_sparse;  // the update still needs to know
       cc.prev_sparse = 0;  // the sparse q_1 was consumed by this iteration's product
       cc.pa = pa;
       cc.xb = xb;
@@ -411,16 +422,20 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
 
 // W = Y - alpha sig U_cur for running columns (in place over Y), the start
 // vector for refilled columns, zero for idle ones; per-block sum d W^2.
+// ro >= 1: also per-block sum d W (slab 0 of rpart); ro == 2: sum d W U_cur and
+// sum d W U_prev (slabs 1 and 2), the coefficients of the re-orthogonalisation.
 // GRAD: also advance the potential of running (and just-stopped) columns,
 // p = sig U_cur + pa p, x = x + xb p (arrays P, X of the same shape).
 template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const double *__restrict__ deg,
                                                           const VT *__restrict__ Ucur,
+                                                          const VT *__restrict__ Uprev,
                                                           VT *__restrict__ Y,
                                                           const ColCtrl *__restrict__ ctrl,
                                                           double *__restrict__ part, int32_t ldp,
                                                           const int32_t *__restrict__ active,
-                                                          double *__restrict__ P, double *__restrict__ X) {
+                                                          double *__restrict__ P, double *__restrict__ X,
+                                                          int32_t ro, double *__restrict__ rpart) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -431,8 +446,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
   VT coef[VEC], vs[VEC], vt[VEC], sig[VEC];
   double pa[VEC], xb[VEC];
   int32_t mode[VEC], cs[VEC], ct[VEC];
+  bool psp[VEC];
   bool pot = false;
-  double acc[VEC];
+  double acc[VEC], a1[VEC], ac[VEC], ap[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
     const ColCtrl &cc = ctrl[c0 + v];
@@ -445,7 +461,8 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     mode[v] = cc.mode;
     cs[v] = cc.s;
     ct[v] = cc.t;
-    acc[v] = 0.0;
+    psp[v] = cc.upd_sparse != 0;
+    acc[v] = a1[v] = ac[v] = ap[v] = 0.0;
     pot = pot || mode[v] == COL_RUN || mode[v] == COL_FINAL;
   }
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
@@ -454,16 +471,25 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     const V y = vload<VT, VEC>(Y + (size_t)r * B + c0);
     const V uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
     const double dr = deg[r];
+    V up;
+    if (ro == 2) up = vload<VT, VEC>(Uprev + (size_t)r * B + c0);
     V o;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       VT x;
       if (mode[v] == COL_RUN) {
         x = y.v[v] - coef[v] * uc.v[v];
-        acc[v] += dr * ((double)x * (double)x);
-      } else if (mode[v] == COL_REFILL) {
-        x = VT(0);  // the first iteration's vector is scattered by k_first_batch
+        const double dx = dr * (double)x;
+        acc[v] += dx * (double)x;
+        if (ro >= 1) a1[v] += dx;
+        if (ro == 2) {
+          const VT pv = psp[v] ? (r == cs[v] ? vs[v] : (r == ct[v] ? vt[v] : VT(0))) : up.v[v];
+          ac[v] += dx * (double)uc.v[v];
+          ap[v] += dx * (double)pv;
+        }
       } else {
+        // refilled columns: the first iteration's vector is scattered by
+        // k_first_batch; idle and finished columns hold zeros
         x = VT(0);
       }
       o.v[v] = x;
@@ -485,6 +511,92 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
         vstore<double, VEC>(X + (size_t)r * B + c0, xv);
       }
     }
+  }
+  block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
+  if (ro >= 1) block_column_partials<B, VEC>(a1, sm, rpart, ldp, blockIdx.x);
+  if (ro == 2) {
+    block_column_partials<B, VEC>(ac, sm, rpart + (size_t)B * ldp, ldp, blockIdx.x);
+    block_column_partials<B, VEC>(ap, sm, rpart + 2 * (size_t)B * ldp, ldp, blockIdx.x);
+  }
+}
+
+// Coefficients of the re-orthogonalisation of every running column from the
+// column sums of k_update (sums[k * B + j], slab k), in terms of the stored
+// vectors: the components of W along u_1 (the constant vector in the scaled
+// basis), q_i = sig_cur U_cur and q_{i-1} = sig_prev U_prev are
+// (sum d W)/vol, sig_cur^2 sum d W U_cur and sig_prev^2 sum d W U_prev.
+__global__ void k_reorth_coef(int32_t B, int32_t ro, double vol, const double *__restrict__ sums,
+                              const LzState *__restrict__ st, ColCtrl *__restrict__ ctrl,
+                              const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  const int j = threadIdx.x;
+  if (j >= B) return;
+  ColCtrl cc = ctrl[j];
+  const LzState &S = st[j];
+  const bool run = cc.mode == COL_RUN;
+  cc.ro_mu = run ? sums[j] / vol : 0.0;
+  cc.ro_c = run && ro == 2 ? S.sig_cur * S.sig_cur * sums[B + j] : 0.0;
+  cc.ro_p = run && ro == 2 ? S.sig_prev * S.sig_prev * sums[2 * B + j] : 0.0;
+  ctrl[j] = cc;
+}
+
+// W -= ro_mu + ro_c U_cur + ro_p U_prev for running columns; per-block sum d W^2.
+template <typename VT, int B>
+__global__ __launch_bounds__(SHORT_THREADS) void k_reorth_apply(int32_t n, const double *__restrict__ deg,
+                                                                const VT *__restrict__ Ucur,
+                                                                const VT *__restrict__ Uprev,
+                                                                VT *__restrict__ Y,
+                                                                const ColCtrl *__restrict__ ctrl,
+                                                                double *__restrict__ part, int32_t ldp,
+                                                                const int32_t *__restrict__ active,
+                                                                int32_t ro) {
+  if (*active == 0) return;
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  using V = VecN<VT, VEC>;
+  __shared__ double sm[(SHORT_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  VT mu[VEC], kc[VEC], kp[VEC], vs[VEC], vt[VEC];
+  int32_t cs[VEC], ct[VEC];
+  bool run[VEC], psp[VEC];
+  double acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const ColCtrl &cc = ctrl[c0 + v];
+    run[v] = cc.mode == COL_RUN;
+    mu[v] = (VT)cc.ro_mu;
+    kc[v] = (VT)cc.ro_c;
+    kp[v] = (VT)cc.ro_p;
+    vs[v] = (VT)cc.vs;
+    vt[v] = (VT)cc.vt;
+    cs[v] = cc.s;
+    ct[v] = cc.t;
+    psp[v] = cc.upd_sparse != 0;
+    acc[v] = 0.0;
+  }
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t r = gw * S::RPW + sub; r < n; r += nwv * S::RPW) {
+    V w = vload<VT, VEC>(Y + (size_t)r * B + c0);
+    V uc, up;
+    if (ro == 2) {
+      uc = vload<VT, VEC>(Ucur + (size_t)r * B + c0);
+      up = vload<VT, VEC>(Uprev + (size_t)r * B + c0);
+    }
+    const double dr = deg[r];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      if (!run[v]) continue;
+      VT x = w.v[v] - mu[v];
+      if (ro == 2) {
+        const VT pv = psp[v] ? (r == cs[v] ? vs[v] : (r == ct[v] ? vt[v] : VT(0))) : up.v[v];
+        x -= kc[v] * uc.v[v] + kp[v] * pv;
+      }
+      w.v[v] = x;
+      acc[v] += dr * ((double)x * (double)x);
+    }
+    vstore<VT, VEC>(Y + (size_t)r * B + c0, w);
   }
   block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
 }
@@ -775,11 +887,13 @@ struct BatchWork {
   int32_t grid_short = 0, grid_upd = 0;
   // buffers sized for the widest run so far
   size_t vec_bytes = 0;
-  void *X[2] = {nullptr, nullptr};
+  void *X[3] = {nullptr, nullptr, nullptr};  // q_{i-1}, q_i and the new vector rotate
   int32_t Bcap = 0;
   double *part = nullptr;  // [Bcap][ldp]
   int32_t ldp = 0;
   double *colsum = nullptr;  // [Bcap]
+  double *rpart = nullptr;   // re-orthogonalisation partials [3][Bcap][ldp]
+  double *rsum = nullptr;    // [3 * 256]
   // gradient mode: search directions and potentials (n x B each), edge accumulator
   void *P = nullptr, *Xp = nullptr;
   size_t pot_bytes = 0;
@@ -799,10 +913,11 @@ void batch_free(rd_graph g) {
   if (!bw) return;
   dev_free(bw->witem_row);
   dev_free(bw->long_rows);
-  dev_free(bw->X[0]);
-  dev_free(bw->X[1]);
+  for (void *x : bw->X) dev_free(x);
   dev_free(bw->part);
   dev_free(bw->colsum);
+  dev_free(bw->rpart);
+  dev_free(bw->rsum);
   dev_free(bw->P);
   dev_free(bw->Xp);
   dev_free(bw->gacc);
@@ -874,25 +989,32 @@ static BatchWork *batch_get(rd_graph g) {
 static void batch_reserve(rd_graph g, BatchWork *bw, int32_t B, size_t elem) {
   const size_t need = (size_t)g->n * B * elem;
   if (need > bw->vec_bytes) {
-    dev_free(bw->X[0]);
-    dev_free(bw->X[1]);
-    bw->X[0] = bw->X[1] = nullptr;
+    for (void *&x : bw->X) {
+      dev_free(x);
+      x = nullptr;
+    }
     bw->vec_bytes = 0;
-    bw->X[0] = dev_alloc(need);
-    bw->X[1] = dev_alloc(need);
+    for (void *&x : bw->X) x = dev_alloc(need);
     bw->vec_bytes = need;
   }
   if (B > bw->Bcap) {
     dev_free(bw->part);
-    bw->part = nullptr;
+    dev_free(bw->rpart);
+    bw->part = bw->rpart = nullptr;
     bw->part = (double *)dev_alloc((size_t)B * bw->ldp * sizeof(double));
     bw->Bcap = B;
   }
 }
 
+// Partial and column-sum buffers of the re-orthogonalisation (on first use).
+static void reorth_reserve(BatchWork *bw) {
+  if (!bw->rpart) bw->rpart = (double *)dev_alloc(3 * (size_t)bw->Bcap * bw->ldp * sizeof(double));
+  if (!bw->rsum) bw->rsum = (double *)dev_alloc(3 * 256 * sizeof(double));
+}
+
 template <typename VT, int B, bool WEIGHTED>
-static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStream_t st,
-                        const int32_t *active, bool prof = false) {
+static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Uprev, VT *Y,
+                        hipStream_t st, const int32_t *active, bool prof = false) {
   const VT *w = nullptr;
   const VT *invdeg;
   if constexpr (sizeof(VT) == 8) {
@@ -908,8 +1030,8 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
     RD_HIP(hipEventRecord(ev.first, st));
   }
   hipLaunchKernelGGL((k_spmm_short<VT, B, WEIGHTED>), dim3(bw->grid_short), dim3(SHORT_THREADS), 0, st,
-                     bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
-                     bw->part, bw->ldp, active);
+                     bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Uprev, Y,
+                     bw->ctrl, bw->part, bw->ldp, active);
   if (prof) {
     RD_HIP(hipEventRecord(ev.second, st));
     const double sv = sizeof(VT);
@@ -920,8 +1042,8 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, VT *Y, hipStr
   }
   if (bw->nlong > 0)
     hipLaunchKernelGGL((k_spmm_long<VT, B, WEIGHTED>), dim3(bw->nlong), dim3(LONG_THREADS), 0, st,
-                       bw->long_rows, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Y, bw->ctrl,
-                       bw->part, bw->ldp, bw->grid_short, active);
+                       bw->long_rows, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Uprev, Y,
+                       bw->ctrl, bw->part, bw->ldp, bw->grid_short, active);
 }
 
 template <typename VT, int B, bool GRAD>
@@ -932,24 +1054,36 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
 }
 
 template <typename VT, int B, bool GRAD>
-static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, const RunParams &prm,
-                                    const int32_t *ps, const int32_t *pt, rd_result *out,
-                                    hipStream_t st, bool prof) {
+static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, int prv, int nxt,
+                                    const RunParams &prm, const int32_t *ps, const int32_t *pt,
+                                    rd_result *out, hipStream_t st, bool prof) {
   const VT *Ucur = (const VT *)bw->X[cur];
-  VT *Y = (VT *)bw->X[1 - cur];
+  const VT *Uprev = (const VT *)bw->X[prv];
+  VT *Y = (VT *)bw->X[nxt];
+  const int32_t *active = bw->qstate + 1;
   if (g->unit)
-    launch_spmm<VT, B, false>(g, bw, Ucur, Y, st, bw->qstate + 1, prof);
+    launch_spmm<VT, B, false>(g, bw, Ucur, Uprev, Y, st, active, prof);
   else
-    launch_spmm<VT, B, true>(g, bw, Ucur, Y, st, bw->qstate + 1, prof);
+    launch_spmm<VT, B, true>(g, bw, Ucur, Uprev, Y, st, active, prof);
   hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
-                     bw->grid_short + bw->nlong, bw->colsum, bw->qstate + 1);
+                     bw->grid_short + bw->nlong, bw->colsum, active);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
   hipLaunchKernelGGL((k_update<VT, B, GRAD>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     g->deg, Ucur, Y, bw->ctrl, bw->part, bw->ldp, bw->qstate + 1, (double *)bw->P,
-                     (double *)bw->Xp);
+                     g->deg, Ucur, Uprev, Y, bw->ctrl, bw->part, bw->ldp, active, (double *)bw->P,
+                     (double *)bw->Xp, prm.reorth, bw->rpart);
+  if (prm.reorth > 0) {
+    // column sums of the three coefficient slabs (rpart holds [3][B][ldp])
+    hipLaunchKernelGGL(k_col_sum, dim3(3 * B), dim3(COL_THREADS), 0, st, bw->rpart, bw->ldp,
+                       bw->grid_upd, bw->rsum, active);
+    hipLaunchKernelGGL(k_reorth_coef, dim3(1), dim3(256), 0, st, B, prm.reorth, g->vol,
+                       (const double *)bw->rsum, (const LzState *)bw->st, bw->ctrl, active);
+    hipLaunchKernelGGL((k_reorth_apply<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                       g->deg, Ucur, Uprev, Y, (const ColCtrl *)bw->ctrl, bw->part, bw->ldp, active,
+                       prm.reorth);
+  }
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
-                     bw->st, bw->ctrl, bw->qstate + 1);
+                     bw->st, bw->ctrl, active);
   launch_first<VT, B, GRAD>(g, bw, Y, st);
 }
 
@@ -961,24 +1095,31 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
                            const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
                            bool prof) {
   batch_reserve(g, bw, B, sizeof(VT));
+  if (prm.reorth > 0) reorth_reserve(bw);
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   // fill the slots: control with every column idle pops the first B pairs,
   // then the update writes their start vectors (and zeros elsewhere)
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
-                     bw->qstate + 1, (double *)nullptr, (double *)nullptr);
+                     g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
+                     bw->part, bw->ldp, bw->qstate + 1, (double *)nullptr, (double *)nullptr, 0,
+                     (double *)nullptr);
   launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
   RD_HIP(hipGetLastError());
-  int cur = 0;
+  // every column starts from the sparse q_1, so the first product reads no
+  // previous vector; X[0] holds w_1
+  int prv = 1, cur = 0, nxt = 2;
   int64_t iters = 0;
   int chunk = 4;
   const int64_t cap = (int64_t)prm.max_iters * ((npairs + B - 1) / B + 1) + 16;
   for (;;) {
     for (int j = 0; j < chunk; ++j) {
-      enqueue_batch_iteration<VT, B, GRAD>(g, bw, cur, prm, ps, pt, out, st, prof);
-      cur ^= 1;
+      enqueue_batch_iteration<VT, B, GRAD>(g, bw, cur, prv, nxt, prm, ps, pt, out, st, prof);
+      const int old_prv = prv;
+      prv = cur;
+      cur = nxt;
+      nxt = old_prv;
     }
     iters += chunk;
     RD_HIP(hipGetLastError());
@@ -1104,14 +1245,19 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   batch_reserve(g, bw, B, sizeof(VT));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     g->deg, (const VT *)bw->X[1], (VT *)bw->X[0], bw->ctrl, bw->part, bw->ldp,
-                     bw->qstate + 3, (double *)nullptr, (double *)nullptr);
+                     g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
+                     bw->part, bw->ldp, bw->qstate + 3, (double *)nullptr, (double *)nullptr, 0,
+                     (double *)nullptr);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
   auto once = [&]() {
-    if (g->unit) launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st, bw->qstate + 3);
-    else launch_spmm<VT, B, true>(g, bw, (const VT *)bw->X[0], (VT *)bw->X[1], st, bw->qstate + 3);
+    if (g->unit)
+      launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (const VT *)bw->X[2], (VT *)bw->X[1], st,
+                                bw->qstate + 3);
+    else
+      launch_spmm<VT, B, true>(g, bw, (const VT *)bw->X[0], (const VT *)bw->X[2], (VT *)bw->X[1], st,
+                               bw->qstate + 3);
   };
   once();
   RD_HIP(hipEventRecord(e0, st));
@@ -1237,7 +1383,7 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
       return RD_OK;
     }
     if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
-    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
+    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
     const bool prof = opt.flags & RD_PROFILE;
     if (opt.refine) {
       // groups of B pairs with potentials, r reported as the FP64 energy
@@ -1324,7 +1470,7 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
     if (B == 0) B = autotune_width(g, bw, opt.precision, std::max(npairs, 1), st);
     RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
-    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs};
+    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
     if (opt.precision == RD_F64)
       grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st, opt.flags & RD_PROFILE);
     else

@@ -107,6 +107,7 @@ __device__ __forceinline__ void scalar_after_beta(LzState &S, double bb, double 
     return;
   }
   S.prev_coef = beta_next * S.sig_cur;
+  S.sig_prev = S.sig_cur;
   S.sig_cur = 1.0 / beta_next;
   S.beta = beta_next;
   if (S.fixed_k > 0 && i >= S.fixed_k) S.status = LZ_DONE;
@@ -118,6 +119,8 @@ __device__ __forceinline__ void state_start(LzState &S, int32_t s, int32_t t, do
                                             int32_t err_mode, int32_t pair) {
   S.c = c;
   S.sig_cur = 1.0;
+  S.sig_prev = 0.0;
+  S.ro_mu = S.ro_c = S.ro_p = 0.0;
   S.prev_coef = 0.0;
   S.beta = 0.0;
   S.alpha = 0.0;

@@ -11,11 +11,14 @@
 // Each vector is stored unnormalised together with a scale (q_i = sig * U_i),
 // so the division by beta_{i+1} is applied when the vector is next read.
 //
-// One iteration = four launches on one stream:
+// Three vector buffers rotate (q_{i-1}, q_i and the new vector). One iteration
+// = four launches on one stream:
 //   k_spmv          y = sig_i D^{-1} W U_i - beta_i q_{i-1}   (+ per-block <y, q_i>_D)
 //   k_reduce_alpha  alpha_i, LDL^T update of I - T_i, r_hat_i, stopping test
 //   k_update        w = y - alpha_i q_i                       (+ per-block ||w||_D^2)
 //   k_reduce_beta   beta_{i+1}, breakdown test, next scales
+// With re-orthogonalisation, k_update also sums the coefficients and
+// k_reorth_coef + k_reorth_apply remove the components before k_reduce_beta.
 // (The partial sums are combined by separate one-block launches: a last-block
 // reduction inside the producing kernel needs a device-scope release per block,
 // which writes back the whole L2 of its XCD and made the product 6x slower.)
@@ -57,8 +60,8 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return block_sum(a, sm);
 }
 
-// y_u = sig (1/d_u) sum_v w_uv U_cur[v] - prev_coef U_prev[u], written over
-// U_prev[u]; per-block partial of sum_u d_u y_u (sig U_cur[u]).
+// y_u = sig (1/d_u) sum_v w_uv U_cur[v] - prev_coef U_prev[u] into Y (the third
+// vector buffer); per-block partial of sum_u d_u y_u (sig U_cur[u]).
 //
 // Multi-row blocks run in three phases so no global load sits on a serial
 // chain: (1) stage the block's row offsets and the gathered products
@@ -70,8 +73,8 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     const int32_t *__restrict__ blk_row, const int8_t *__restrict__ blk_lanes,
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const VT *__restrict__ w, const VT *__restrict__ invdeg, const double *__restrict__ deg,
-    const VT *__restrict__ Ucur, VT *__restrict__ Y, double *__restrict__ part,
-    const LzState *__restrict__ st) {
+    const VT *__restrict__ Ucur, const VT *__restrict__ Uprev, VT *__restrict__ Y,
+    double *__restrict__ part, const LzState *__restrict__ st) {
   if (st->status != LZ_RUNNING) return;
   __shared__ VT vals[BLOCK_NNZ];
   __shared__ VT rsum[BLOCK_ROWS];
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     a = block_sum(a, vred);
     if (tid == 0) {
       VT y = sig * a * invdeg[r0];
-      if (has_prev) y -= pc * Y[r0];
+      if (has_prev) y -= pc * Uprev[r0];
       Y[r0] = y;
       apart = deg[r0] * (double)y * ((double)sig * (double)Ucur[r0]);
     }
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
       e_id = invdeg[r];
       e_u = Ucur[r];
       e_d = deg[r];
-      if (has_prev) e_y = Y[r];
+      if (has_prev) e_y = Uprev[r];
     }
     // at most BLOCK_NNZ entries: every index load, then every gather, in flight at once
     constexpr int PER = BLOCK_NNZ / SPMV_THREADS;
@@ -180,18 +183,88 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_alpha(const double *__re
 }
 
 
-// w = y - alpha_i sig_i U_cur, in place over y; per-block partial of sum d w^2.
-template <typename VT>
+// w = y - alpha_i sig_i U_cur, in place over y; per-block partials (slab j at
+// part + j * nb): sum d w^2; RO >= 1: sum d w; RO == 2: sum d w U_cur and
+// sum d w U_prev (the coefficients of the re-orthogonalisation).
+template <typename VT, int RO>
 __global__ __launch_bounds__(UPD_THREADS) void k_update(int32_t n, const double *__restrict__ deg,
                                                         const VT *__restrict__ Ucur,
+                                                        const VT *__restrict__ Uprev,
                                                         VT *__restrict__ Y, double *__restrict__ part,
                                                         const LzState *__restrict__ st) {
   if (st->status != LZ_RUNNING) return;
   __shared__ double red[UPD_THREADS / 64];
   const VT a = (VT)(st->alpha * st->sig_cur);
+  double acc = 0.0, a1 = 0.0, ac = 0.0, ap = 0.0;
+  for (int32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < n; i += gridDim.x * UPD_THREADS) {
+    const VT u = Ucur[i];
+    VT x = Y[i] - a * u;
+    Y[i] = x;
+    const double d = deg[i], dx = d * (double)x;
+    acc += dx * (double)x;
+    if constexpr (RO >= 1) a1 += dx;
+    if constexpr (RO == 2) {
+      ac += dx * (double)u;
+      ap += dx * (double)Uprev[i];
+    }
+  }
+  const int nb = gridDim.x;
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if constexpr (RO >= 1) {
+    a1 = block_sum(a1, red);
+    if (threadIdx.x == 0) part[nb + blockIdx.x] = a1;
+  }
+  if constexpr (RO == 2) {
+    ac = block_sum(ac, red);
+    ap = block_sum(ap, red);
+    if (threadIdx.x == 0) {
+      part[2 * nb + blockIdx.x] = ac;
+      part[3 * nb + blockIdx.x] = ap;
+    }
+  }
+}
+
+// Coefficients of the re-orthogonalisation from the partials of k_update (fixed
+// order), in terms of the stored vectors: with S1 = sum d w, Sc = sum d w U_cur,
+// Sp = sum d w U_prev, the components of w along u_1 (in the scaled basis the
+// constant vector), q_i = sig_cur U_cur and q_{i-1} = sig_prev U_prev are
+// removed by w -= (S1/vol) 1 + sig_cur^2 Sc U_cur + sig_prev^2 Sp U_prev.
+template <int RO>
+__global__ __launch_bounds__(RED_THREADS) void k_reorth_coef(const double *__restrict__ part, int nb,
+                                                             double vol, LzState *__restrict__ st) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ double sm[RED_THREADS / 64];
+  const double s1 = sum_partials(part + nb, nb, sm);
+  double sc = 0.0, sp = 0.0;
+  if constexpr (RO == 2) {
+    sc = sum_partials(part + 2 * nb, nb, sm);
+    sp = sum_partials(part + 3 * nb, nb, sm);
+  }
+  if (threadIdx.x == 0) {
+    LzState S = *st;
+    S.ro_mu = s1 / vol;
+    S.ro_c = S.sig_cur * S.sig_cur * sc;
+    S.ro_p = S.sig_prev * S.sig_prev * sp;
+    *st = S;
+  }
+}
+
+// w -= ro_mu 1 + ro_c U_cur + ro_p U_prev, per-block partial of sum d w^2.
+template <typename VT, int RO>
+__global__ __launch_bounds__(UPD_THREADS) void k_reorth_apply(int32_t n, const double *__restrict__ deg,
+                                                              const VT *__restrict__ Ucur,
+                                                              const VT *__restrict__ Uprev,
+                                                              VT *__restrict__ Y,
+                                                              double *__restrict__ part,
+                                                              const LzState *__restrict__ st) {
+  if (st->status != LZ_RUNNING) return;
+  __shared__ double red[UPD_THREADS / 64];
+  const VT mu = (VT)st->ro_mu, cc = (VT)st->ro_c, cp = (VT)st->ro_p;
   double acc = 0.0;
   for (int32_t i = blockIdx.x * UPD_THREADS + threadIdx.x; i < n; i += gridDim.x * UPD_THREADS) {
-    VT x = Y[i] - a * Ucur[i];
+    VT x = Y[i] - mu;
+    if constexpr (RO == 2) x -= cc * Ucur[i] + cp * Uprev[i];
     Y[i] = x;
     acc += deg[i] * ((double)x * (double)x);
   }
@@ -276,7 +349,7 @@ __global__ __launch_bounds__(256) void k_first(const int32_t *__restrict__ row_p
 
 struct PlainWork {
   int32_t n = 0;
-  void *U[2] = {nullptr, nullptr};  // n doubles each (room for either precision)
+  void *U[3] = {nullptr, nullptr, nullptr};  // n doubles each (room for either precision)
   double *part = nullptr;
   int32_t npart = 0;
   LzState *st = nullptr;
@@ -288,8 +361,7 @@ struct PlainWork {
 void plain_free(rd_graph g) {
   PlainWork *pw = g->plain;
   if (!pw) return;
-  dev_free(pw->U[0]);
-  dev_free(pw->U[1]);
+  for (void *u : pw->U) dev_free(u);
   dev_free(pw->part);
   dev_free(pw->st);
   if (pw->st_host) (void)hipHostFree(pw->st_host);
@@ -304,12 +376,13 @@ static PlainWork *plain_get(rd_graph g) {
     pw->n = g->n;
     pw->U[0] = dev_alloc((size_t)g->n * sizeof(double));
     pw->U[1] = dev_alloc((size_t)g->n * sizeof(double));
+    pw->U[2] = dev_alloc((size_t)g->n * sizeof(double));
     int dev_cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
     pw->upd_blocks = std::max(1, std::min<int>((g->n + UPD_THREADS * 4 - 1) / (UPD_THREADS * 4),
                                                dev_cus * 8));
-    pw->npart = std::max(g->nblk, pw->upd_blocks);
+    pw->npart = std::max(g->nblk, 4 * pw->upd_blocks);  // four slabs for the re-orthogonalisation
     pw->part = (double *)dev_alloc((size_t)pw->npart * sizeof(double));
     pw->st = (LzState *)dev_alloc(sizeof(LzState));
     RD_HIP(hipHostMalloc((void **)&pw->st_host, sizeof(LzState), hipHostMallocDefault));
@@ -322,11 +395,27 @@ static PlainWork *plain_get(rd_graph g) {
   return pw;
 }
 
+template <typename VT, int RO>
+static void enqueue_update(rd_graph g, PlainWork *pw, const VT *Ucur, const VT *Uprev, VT *Y,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_update<VT, RO>), dim3(pw->upd_blocks), dim3(UPD_THREADS), 0, st, g->n, g->deg,
+                     Ucur, Uprev, Y, pw->part, pw->st);
+  if constexpr (RO > 0) {
+    hipLaunchKernelGGL(k_reorth_coef<RO>, dim3(1), dim3(RED_THREADS), 0, st, pw->part, pw->upd_blocks,
+                       g->vol, pw->st);
+    hipLaunchKernelGGL((k_reorth_apply<VT, RO>), dim3(pw->upd_blocks), dim3(UPD_THREADS), 0, st, g->n,
+                       g->deg, Ucur, Uprev, Y, pw->part, pw->st);
+  }
+}
+
+// One dense iteration: product of U[cur] (q_i) with U[prv] (q_{i-1}) into U[nxt].
 template <typename VT>
-static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st, double *tr_alpha,
-                              double *tr_beta, double *tr_rhat, bool prof) {
+static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, int prv, int nxt, int reorth,
+                              hipStream_t st, double *tr_alpha, double *tr_beta, double *tr_rhat,
+                              bool prof) {
   const VT *Ucur = (const VT *)pw->U[cur];
-  VT *Y = (VT *)pw->U[1 - cur];
+  const VT *Uprev = (const VT *)pw->U[prv];
+  VT *Y = (VT *)pw->U[nxt];
   std::pair<hipEvent_t, hipEvent_t> ev{};
   if (prof) {
     ev = g->timer[1].next();
@@ -335,11 +424,11 @@ static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st
   if (g->unit)
     hipLaunchKernelGGL((k_spmv<VT, false>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
                        g->blk_lanes, g->row_ptr, g->col, (const VT *)nullptr,
-                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Y, pw->part, pw->st);
+                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Uprev, Y, pw->part, pw->st);
   else
     hipLaunchKernelGGL((k_spmv<VT, true>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
                        g->blk_lanes, g->row_ptr, g->col, VecTraits<VT>::w(g),
-                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Y, pw->part, pw->st);
+                       VecTraits<VT>::invdeg(g), g->deg, Ucur, Uprev, Y, pw->part, pw->st);
   if (prof) {
     RD_HIP(hipEventRecord(ev.second, st));
     const double sv = sizeof(VT);
@@ -348,8 +437,9 @@ static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, hipStream_t st
   }
   hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(RED_THREADS), 0, st, pw->part, g->nblk, pw->st,
                      tr_alpha, tr_rhat);
-  hipLaunchKernelGGL(k_update<VT>, dim3(pw->upd_blocks), dim3(UPD_THREADS), 0, st, g->n, g->deg,
-                     Ucur, Y, pw->part, pw->st);
+  if (reorth == 0) enqueue_update<VT, 0>(g, pw, Ucur, Uprev, Y, st);
+  else if (reorth == 1) enqueue_update<VT, 1>(g, pw, Ucur, Uprev, Y, st);
+  else enqueue_update<VT, 2>(g, pw, Ucur, Uprev, Y, st);
   hipLaunchKernelGGL(k_reduce_beta, dim3(1), dim3(RED_THREADS), 0, st, pw->part, pw->upd_blocks,
                      pw->st, tr_beta);
 }
@@ -367,13 +457,17 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
   RD_HIP(hipGetLastError());
   const int cap = o.fixed_k > 0 ? o.fixed_k : o.max_iters;
   // iteration 1 is done; the dense iterations start from U[1] (w_1) and U[0] (q_1)
-  int done_iters = 1, cur = 1;
+  int done_iters = 1, prv = 0, cur = 1, nxt = 2;
   int chunk = o.fixed_k > 0 ? o.fixed_k - 1 : std::max(4, std::min(pw->last_k, 64));
   for (;;) {
     const int todo = std::min(chunk, cap - done_iters);
     for (int j = 0; j < todo; ++j) {
-      enqueue_iteration<VT>(g, pw, cur, st, tr_alpha, tr_beta, tr_rhat, o.flags & RD_PROFILE);
-      cur ^= 1;
+      enqueue_iteration<VT>(g, pw, cur, prv, nxt, o.reorth, st, tr_alpha, tr_beta, tr_rhat,
+                            o.flags & RD_PROFILE);
+      const int old_prv = prv;
+      prv = cur;
+      cur = nxt;
+      nxt = old_prv;
     }
     RD_HIP(hipGetLastError());
     done_iters += todo;

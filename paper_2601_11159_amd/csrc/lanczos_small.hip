@@ -103,7 +103,7 @@ static size_t small_lds_limit(rd_graph g) {
 }
 
 bool small_eligible(rd_graph g, const rd_options &o) {
-  if (o.flags & RD_GENERAL_PATH) return false;
+  if ((o.flags & RD_GENERAL_PATH) || o.reorth > 0) return false;
   const size_t vt = o.precision == RD_F64 ? sizeof(double) : sizeof(float);
   return 2 * (size_t)g->n * vt <= small_lds_limit(g);
 }

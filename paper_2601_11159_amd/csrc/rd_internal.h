@@ -43,6 +43,7 @@ constexpr int RD_HIST = 16;  // ring of recent r_hat values for the stopping est
 struct LzState {
   double c;          // 1/d_s + 1/d_t
   double sig_cur;    // q_i = sig_cur * U_cur (scale-on-read normalisation)
+  double sig_prev;   // q_{i-1} = sig_prev * U_prev
   double prev_coef;  // beta_i * sig_prev: coefficient of U_prev in the recurrence (0 when i = 1)
   double beta;       // beta_i
   double alpha;      // alpha_i of the current iteration
@@ -52,6 +53,7 @@ struct LzState {
   double rhat;       // c * g
   double err_est;    // stopping estimate (absolute)
   double tol;        // stopping tolerance (relative or absolute per err_mode)
+  double ro_mu, ro_c, ro_p;  // re-orthogonalisation: w -= ro_mu 1 + ro_c U_cur + ro_p U_prev
   double hist[RD_HIST];
   int32_t k;         // iterations completed
   int32_t status;    // LZ_*
@@ -90,6 +92,7 @@ struct rd_graph_s {
   int64_t m = 0, nnz = 0;
   bool unit = true;
   int32_t max_deg = 0;
+  double vol = 0.0;  // sum of the weighted degrees
 
   int32_t *row_ptr = nullptr;  // [n+1]
   int32_t *col = nullptr;      // [nnz] neighbour ids, ascending within a row

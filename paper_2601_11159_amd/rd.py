@@ -50,6 +50,7 @@ class RdOptions(ctypes.Structure):
         ("err_mode", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("refine", ctypes.c_int32),
+        ("reorth", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

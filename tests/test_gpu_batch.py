@@ -160,3 +160,38 @@ def test_autotuned_width_runs():
     for p in range(0, 300, 50):
         run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-10, A=A, d=d)
         assert abs(out["r"][p] - run.r) / run.r <= 1e-4
+
+
+@pytest.mark.parametrize("ro", [1, 2])
+@pytest.mark.parametrize("prec,eps,bar", [(rd.RD_F64, 1e-10, 1e-8), (rd.RD_F32, 1e-5, 1e-3)])
+def test_reorth_batch_matches_truth_and_plain(ro, prec, eps, bar):
+    # uneven pairs with refill (more pairs than columns) and s == t entries
+    g = I.chung_lu(4000, 2.3, 8.0, seed=61)
+    s, t = I.uniform_pairs(g.n, 90, seed=62)
+    t[11] = s[11]
+    mask = s != t
+    truth = np.zeros(len(s))
+    truth[mask] = D.rd_all(g, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = G.query_batch(s, t, eps, _opts(precision=prec, block_width=32, reorth=ro))
+    assert np.all(out["status"] == rd.RD_OK)
+    assert out["r"][11] == 0.0
+    err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+    assert err.max() <= bar, err.max()
+    if prec == rd.RD_F64:
+        o = rd.rd_default_options(reorth=ro, flags=rd.RD_GENERAL_PATH)
+        for p in range(0, 90, 13):
+            if s[p] == t[p]:
+                continue
+            single = G.query(int(s[p]), int(t[p]), eps, o)
+            assert abs(single.iters - out["iters"][p]) <= 1
+            assert single.r == pytest.approx(out["r"][p], rel=1e-9)
+
+
+def test_reorth_gradient_matches_dense():
+    g = I.random_connected(700, extra=4000, seed=63, weighted=True)
+    s, t = I.uniform_pairs(g.n, 40, seed=64)
+    ref = D.grad_edges(g, D.pinv(D.laplacian(g)), s, t)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    fwd, gw = G.grad_edges(s, t, None, 1e-12, _opts(block_width=32, reorth=2))
+    assert np.linalg.norm(gw - ref) / np.linalg.norm(ref) <= 1e-6

@@ -196,3 +196,37 @@ def test_chung_lu_200k_against_oracle():
         assert res.r == pytest.approx(run.r, rel=1e-10)
         resf = G.query(int(s[p]), int(t[p]), 1e-6, F32)
         assert resf.r == pytest.approx(run.r, rel=1e-5)
+
+
+@pytest.mark.parametrize("ro", [1, 2])
+@pytest.mark.parametrize("prec", [rd.RD_F64, rd.RD_F32])
+def test_reorth_plain_matches_oracle_steps_and_truth(ro, prec):
+    g = I.grid(40, 40)
+    G = _graph(g)
+    A, d = LZ.normalized_adjacency(g)
+    # step parity with the oracle's re-orthogonalised loop
+    o = rd.rd_default_options(precision=prec, reorth=ro)
+    a, b, r = G.query_trace(3, 1500, 60, o)
+    ref = LZ.lanczos_rd(g, 3, 1500, k=60, A=A, d=d, reorth=ro)
+    tol = 1e-10 if prec == rd.RD_F64 else 1e-4
+    np.testing.assert_allclose(a, ref.alpha, rtol=0, atol=tol)
+    np.testing.assert_allclose(b, ref.beta[1:61], rtol=0, atol=tol)
+    # converged values against the dense truth
+    s, t = I.uniform_pairs(g.n, 6, seed=51)
+    truth = D.rd_all(g, s, t)
+    eps = 1e-10 if prec == rd.RD_F64 else 1e-5
+    bar = 1e-8 if prec == rd.RD_F64 else 1e-3
+    for p in range(len(s)):
+        res = G.query(int(s[p]), int(t[p]), eps, o)
+        assert res.status == rd.RD_OK
+        assert res.r == pytest.approx(truth[p], rel=bar)
+
+
+@pytest.mark.parametrize("ro", [1, 2])
+def test_reorth_long_run_past_convergence_stays_at_the_truth(ro):
+    # 3n iterations, far beyond convergence: the estimate stays at |s - t|
+    g = I.path(200)
+    G = _graph(g)
+    out = G.query(3, 150, 1.0, rd.rd_default_options(fixed_k=600, reorth=ro))
+    assert out.iters == 600
+    assert out.r == pytest.approx(147.0, rel=1e-8)

@@ -336,3 +336,48 @@ def test_tridiagonal_solve_matches_dense_inverse():
     beta = np.concatenate([[0.0], rng.uniform(0.05, 0.4, k - 1)])
     T = LZ.tridiag_matrix(alpha, beta)
     assert LZ.tridiag_solve_e1(alpha, beta) == pytest.approx(np.linalg.inv(np.eye(k) - T)[0, 0], rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Optional re-orthogonalisation (not part of Algorithm 3)
+# ----------------------------------------------------------------------------
+
+def test_reorth_removes_the_null_space_component_on_long_runs():
+    # Run far past convergence (k = 3n on a path): without deflation the
+    # Lanczos vectors pick up a large component along u_1 = D^{1/2} 1/sqrt(vol)
+    # (eigenvalue 1 of calA); with reorth >= 1 it stays at rounding level.
+    g = I.path(80)
+    A, d = LZ.normalized_adjacency(g)
+    u1 = np.sqrt(d) / np.sqrt(d.sum())
+    comp = {}
+    for ro in (0, 1, 2):
+        run = LZ.lanczos_rd(g, 0, 40, k=240, A=A, d=d, keep_vectors=True, reorth=ro)
+        comp[ro] = np.abs(u1 @ np.stack(run.V, 1)).max()
+    assert comp[0] > 0.1
+    assert comp[1] < 1e-14 and comp[2] < 1e-14
+
+
+def test_reorth2_keeps_consecutive_vectors_orthogonal():
+    g = I.grid(12, 12)
+    A, d = LZ.normalized_adjacency(g)
+    run = LZ.lanczos_rd(g, 0, 143, k=300, A=A, d=d, keep_vectors=True, reorth=2)
+    V = np.stack(run.V, 1)
+    G = V.T @ V
+    assert np.abs(np.diag(G, 1)).max() < 1e-13
+    assert np.abs(np.diag(G, 2)).max() < 1e-13
+    assert np.abs(np.diag(G) - 1).max() < 1e-13
+
+
+@pytest.mark.parametrize("ro", [1, 2])
+def test_reorth_does_not_change_early_steps_or_the_limit(ro):
+    # every coefficient is zero in exact arithmetic: the first steps agree with
+    # the plain loop to rounding, and the converged value is the dense truth
+    g = I.random_connected(300, 600, seed=3)
+    A, d = LZ.normalized_adjacency(g)
+    a = LZ.lanczos_rd(g, 5, 250, k=10, A=A, d=d)
+    b = LZ.lanczos_rd(g, 5, 250, k=10, A=A, d=d, reorth=ro)
+    np.testing.assert_allclose(b.alpha, a.alpha, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(b.beta, a.beta, rtol=0, atol=1e-14)
+    truth = D.rd_all(g, np.array([5]), np.array([250]))[0]
+    run = LZ.lanczos_rd(g, 5, 250, tol=1e-12, A=A, d=d, reorth=ro)
+    assert run.r == pytest.approx(truth, rel=1e-10)
