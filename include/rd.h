@@ -63,6 +63,12 @@ typedef enum {
                            products gather most often share cache lines. Every argument and
                            result stays in the caller's node ids and edge order. */
 
+#define RD_NO_COMPACT 0x10u /* rd_options.flags: rd_query_batch keeps its block width to the end.
+                               By default, once every pair has started and at most half of the
+                               columns still run, the running columns move to a block of half
+                               the width (repeatedly, down to 16), so a tail of slow pairs does
+                               not pay for idle columns. Results differ only by rounding. */
+
 /* weight / vector dtypes */
 #define RD_F64 0
 #define RD_F32 1
@@ -195,8 +201,9 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
  * length <= 1024 (k_spmm_short); which = 1: the single-pair product (k_spmv);
  * which = 2: the edge pass of rd_grad_edges (k_grad_edges, one launch per
  * group of block_width pairs). Durations come from HIP events recorded around
- * each launch on the stream it runs on. alg_bytes receives the algorithmic
- * bytes of one launch of the last recorded configuration. Products: adjacency
+ * each launch on the stream it runs on. alg_bytes receives the mean
+ * algorithmic bytes per counted launch (a batched run that narrows its block
+ * counts each launch at its own width). Products: adjacency
  * indices (and values, if weighted) of the rows covered, row offsets, the
  * gathered vector block read once, the previous block read and the result
  * block written, and the degree arrays. Edge pass: its work items, the column

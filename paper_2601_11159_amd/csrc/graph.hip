@@ -314,13 +314,15 @@ rd_options resolve_options(rd_graph g, const rd_options *o) {
   return r;
 }
 
-std::pair<hipEvent_t, hipEvent_t> KernelTimer::next() {
+std::pair<hipEvent_t, hipEvent_t> KernelTimer::next(double alg_bytes) {
   if (used == pool.size()) {
     hipEvent_t a, b;
     RD_HIP(hipEventCreate(&a));
     RD_HIP(hipEventCreate(&b));
     pool.push_back({a, b});
+    bytes.push_back(0.0);
   }
+  bytes[used] = alg_bytes;
   return pool[used++];
 }
 
@@ -329,6 +331,7 @@ void KernelTimer::resolve(size_t valid) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pool[i].first, pool[i].second) == hipSuccess) {
       total_ms += ms;
+      total_bytes += bytes[i];
       ++launches;
     } else {
       (void)hipGetLastError();
@@ -343,6 +346,7 @@ void KernelTimer::release() {
     (void)hipEventDestroy(p.second);
   }
   pool.clear();
+  bytes.clear();
   used = 0;
 }
 
@@ -472,8 +476,9 @@ rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *
   KernelTimer &k = g->timer[which];
   if (total_ms) *total_ms = k.total_ms;
   if (launches) *launches = k.launches;
-  if (alg_bytes) *alg_bytes = k.alg_bytes;
+  if (alg_bytes) *alg_bytes = k.launches ? k.total_bytes / (double)k.launches : 0.0;
   k.total_ms = 0;
+  k.total_bytes = 0;
   k.launches = 0;
   return RD_OK;
 }

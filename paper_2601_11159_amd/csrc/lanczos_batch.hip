@@ -937,6 +937,7 @@ struct BatchWork {
   int32_t *qstate = nullptr;       // [4]: queue head, active columns, working iterations, 1
   int32_t *qstate_host = nullptr;  // pinned
   int32_t *flag = nullptr;
+  int32_t *cmap = nullptr;  // [128] source columns of a compaction
   // autotune cache: chosen width per precision
   int32_t tuned[2] = {0, 0};
 };
@@ -959,6 +960,7 @@ void batch_free(rd_graph g) {
   dev_free(bw->ctrl);
   dev_free(bw->qstate);
   dev_free(bw->flag);
+  dev_free(bw->cmap);
   if (bw->qstate_host) (void)hipHostFree(bw->qstate_host);
   delete bw;
   g->batch = nullptr;
@@ -1015,6 +1017,7 @@ static BatchWork *batch_get(rd_graph g) {
   bw->colsum = (double *)dev_alloc(256 * sizeof(double));
   bw->qstate = (int32_t *)dev_alloc(4 * sizeof(int32_t));
   bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
+  bw->cmap = (int32_t *)dev_alloc(128 * sizeof(int32_t));
   RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 4 * sizeof(int32_t), hipHostMallocDefault));
   return bw;
 }
@@ -1059,20 +1062,16 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Upr
   }
   std::pair<hipEvent_t, hipEvent_t> ev{};
   if (prof) {
-    ev = g->timer[0].next();
+    const double sv = sizeof(VT);
+    ev = g->timer[0].next((double)bw->nnz_short * (4.0 + (WEIGHTED ? sv : 0.0)) +
+                          4.0 * ((double)bw->n_short + 2.0 * bw->nwi) +
+                          sv * B * ((double)g->n + 2.0 * bw->n_short) + (sv + 8.0) * (double)bw->n_short);
     RD_HIP(hipEventRecord(ev.first, st));
   }
   hipLaunchKernelGGL((k_spmm_short<VT, B, WEIGHTED>), dim3(bw->grid_short), dim3(SHORT_THREADS), 0, st,
                      bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Uprev, Y,
                      bw->ctrl, bw->part, bw->ldp, active);
-  if (prof) {
-    RD_HIP(hipEventRecord(ev.second, st));
-    const double sv = sizeof(VT);
-    g->timer[0].alg_bytes = (double)bw->nnz_short * (4.0 + (WEIGHTED ? sv : 0.0)) +
-                            4.0 * ((double)bw->n_short + 2.0 * bw->nwi) +
-                            sv * B * ((double)g->n + 2.0 * bw->n_short) +
-                            (sv + 8.0) * (double)bw->n_short;
-  }
+  if (prof) RD_HIP(hipEventRecord(ev.second, st));
   if (bw->nlong > 0)
     hipLaunchKernelGGL((k_spmm_long<VT, B, WEIGHTED>), dim3(bw->nlong), dim3(LONG_THREADS), 0, st,
                        bw->long_rows, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Uprev, Y,
@@ -1086,13 +1085,25 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
                      bw->qstate + 1);
 }
 
+// The three vector blocks of a run: q_{i-1}, q_i and the block the next
+// product writes (they rotate every iteration).
+struct RunBufs {
+  void *prv, *cur, *nxt;
+  void rotate() {
+    void *old = prv;
+    prv = cur;
+    cur = nxt;
+    nxt = old;
+  }
+};
+
 template <typename VT, int B, bool GRAD>
-static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, int prv, int nxt,
+static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb,
                                     const RunParams &prm, const int32_t *ps, const int32_t *pt,
                                     rd_result *out, hipStream_t st, bool prof) {
-  const VT *Ucur = (const VT *)bw->X[cur];
-  const VT *Uprev = (const VT *)bw->X[prv];
-  VT *Y = (VT *)bw->X[nxt];
+  const VT *Ucur = (const VT *)rb.cur;
+  const VT *Uprev = (const VT *)rb.prv;
+  VT *Y = (VT *)rb.nxt;
   const int32_t *active = bw->qstate + 1;
   if (g->unit)
     launch_spmm<VT, B, false>(g, bw, Ucur, Uprev, Y, st, active, prof);
@@ -1120,13 +1131,113 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, int cur, int prv,
   launch_first<VT, B, GRAD>(g, bw, Y, st);
 }
 
+// Tail compaction: the running columns of a B-wide run (their q_i and q_{i-1}
+// and their state) move to columns 0..count-1 of a B/2-wide run, the other
+// columns of which are idle. map[c] is the source column of column c (-1: none),
+// increasing in c, so map[c] >= c.
+template <typename VT, int B>
+__global__ void k_compact_vectors(int32_t n, const int32_t *__restrict__ map,
+                                  const VT *__restrict__ cur, const VT *__restrict__ prv,
+                                  VT *__restrict__ cur2, VT *__restrict__ prv2) {
+  constexpr int H = B / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * H) return;
+  const int64_t r = i / H;
+  const int c = (int)(i - r * H);
+  const int src = map[c];
+  cur2[i] = src >= 0 ? cur[r * B + src] : VT(0);
+  prv2[i] = src >= 0 ? prv[r * B + src] : VT(0);
+}
+
+// In place, by one thread in increasing column order (map[c] >= c, so no
+// source is overwritten before it is read).
+__global__ void k_compact_state(int32_t H, const int32_t *__restrict__ map, LzState *__restrict__ st,
+                                ColCtrl *__restrict__ ctrl) {
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < H; ++c) {
+    const int src = map[c];
+    if (src >= 0) {
+      if (src != c) {
+        st[c] = st[src];
+        ctrl[c] = ctrl[src];
+      }
+    } else {
+      LzState S = st[c];
+      S.status = LZ_IDLE;
+      S.pair = -1;
+      st[c] = S;
+      ColCtrl cc = ctrl[c];
+      cc.mode = COL_IDLE;
+      cc.sig = cc.pc = cc.coef = 0.0;
+      cc.prev_sparse = cc.upd_sparse = 0;
+      ctrl[c] = cc;
+    }
+  }
+}
+
+// Iterate a B-wide run until every column has stopped. Iterations are
+// enqueued in growing chunks and the host reads the queue state in between.
+// Once the pair queue is empty and at most half of the columns still run, the
+// run continues at half the width (compact_ok, down to 16 columns).
+// Returns the number of iterations enqueued.
+template <typename VT, int B, bool GRAD>
+static int64_t batch_loop(rd_graph g, BatchWork *bw, RunBufs rb, int32_t npairs, const int32_t *ps,
+                          const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
+                          bool prof, bool compact_ok, int64_t iters, int64_t cap) {
+  int chunk = 4;
+  for (;;) {
+    for (int j = 0; j < chunk; ++j) {
+      enqueue_batch_iteration<VT, B, GRAD>(g, bw, rb, prm, ps, pt, out, st, prof);
+      rb.rotate();
+    }
+    iters += chunk;
+    RD_HIP(hipGetLastError());
+    RD_HIP(hipMemcpyAsync(bw->qstate_host, bw->qstate, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    if (bw->qstate_host[1] == 0) return iters;
+    RD_REQUIRE(iters < cap, "batched run did not drain (internal error)");
+    if constexpr (B > 16) {
+      if (compact_ok && bw->qstate_host[0] >= npairs && bw->qstate_host[1] <= B / 2) {
+        constexpr int H = B / 2;
+        std::vector<ColCtrl> cc(B);
+        RD_HIP(hipMemcpyAsync(cc.data(), bw->ctrl, B * sizeof(ColCtrl), hipMemcpyDeviceToHost, st));
+        RD_HIP(hipStreamSynchronize(st));
+        int32_t map[256];
+        int count = 0;
+        for (int c = 0; c < B; ++c)
+          if (cc[c].mode == COL_RUN) map[count++] = c;
+        RD_REQUIRE(count <= H, "compaction: more running columns than the narrower block holds");
+        for (int c = count; c < H; ++c) map[c] = -1;
+        RD_HIP(hipMemcpyAsync(bw->cmap, map, H * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        // q_i and q_{i-1} go to the two halves of the free block; the old q_i
+        // block becomes the next product's output
+        VT *cur2 = (VT *)rb.nxt;
+        VT *prv2 = cur2 + (size_t)g->n * H;
+        hipLaunchKernelGGL((k_compact_vectors<VT, B>), dim3(cdiv((int64_t)g->n * H, 256)), dim3(256), 0,
+                           st, g->n, (const int32_t *)bw->cmap, (const VT *)rb.cur, (const VT *)rb.prv,
+                           cur2, prv2);
+        hipLaunchKernelGGL(k_compact_state, dim3(1), dim3(64), 0, st, H, (const int32_t *)bw->cmap,
+                           bw->st, bw->ctrl);
+        RD_HIP(hipGetLastError());
+        RunBufs nb{prv2, cur2, rb.cur};
+        return batch_loop<VT, H, GRAD>(g, bw, nb, npairs, ps, pt, prm, out, st, prof, compact_ok, iters,
+                                       cap);
+      }
+    }
+    // once every pair has started, look at the state more often so the tail
+    // is caught while it can still be narrowed
+    const bool tail = compact_ok && B > 16 && bw->qstate_host[0] >= npairs;
+    chunk = std::min(chunk * 2, tail ? 8 : 64);
+  }
+}
+
 // Run all pairs through B slots. Returns the number of iterations enqueued.
 // GRAD: npairs <= B (no refill) and the potentials of the B runs are
-// accumulated in bw->Xp (bw->P, bw->Xp zeroed by the caller).
+// accumulated in bw->Xp (bw->P, bw->Xp zeroed by the caller); no compaction.
 template <typename VT, int B, bool GRAD = false>
 static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                            const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
-                           bool prof) {
+                           bool prof, bool compact_ok = false) {
   batch_reserve(g, bw, B, sizeof(VT));
   if (prm.reorth > 0) reorth_reserve(bw);
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
@@ -1142,26 +1253,10 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   RD_HIP(hipGetLastError());
   // every column starts from the sparse q_1, so the first product reads no
   // previous vector; X[0] holds w_1
-  int prv = 1, cur = 0, nxt = 2;
-  int64_t iters = 0;
-  int chunk = 4;
+  const RunBufs rb{bw->X[1], bw->X[0], bw->X[2]};
   const int64_t cap = (int64_t)prm.max_iters * ((npairs + B - 1) / B + 1) + 16;
-  for (;;) {
-    for (int j = 0; j < chunk; ++j) {
-      enqueue_batch_iteration<VT, B, GRAD>(g, bw, cur, prv, nxt, prm, ps, pt, out, st, prof);
-      const int old_prv = prv;
-      prv = cur;
-      cur = nxt;
-      nxt = old_prv;
-    }
-    iters += chunk;
-    RD_HIP(hipGetLastError());
-    RD_HIP(hipMemcpyAsync(bw->qstate_host, bw->qstate, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    RD_HIP(hipStreamSynchronize(st));
-    if (bw->qstate_host[1] == 0) break;
-    RD_REQUIRE(iters < cap, "batched run did not drain (internal error)");
-    chunk = std::min(chunk * 2, 64);
-  }
+  const int64_t iters =
+      batch_loop<VT, B, GRAD>(g, bw, rb, npairs, ps, pt, prm, out, st, prof, compact_ok && !GRAD, 0, cap);
   // sparse products enqueued after the last active iteration returned at once
   if (prof) g->timer[0].resolve((size_t)bw->qstate_host[2]);
   return iters;
@@ -1170,13 +1265,13 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
 template <typename VT>
 static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
                               const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
-                              bool prof) {
+                              bool prof, bool compact) {
   switch (B) {
-    case 16: return batch_run_t<VT, 16>(g, bw, npairs, ps, pt, prm, out, st, prof);
-    case 32: return batch_run_t<VT, 32>(g, bw, npairs, ps, pt, prm, out, st, prof);
-    case 64: return batch_run_t<VT, 64>(g, bw, npairs, ps, pt, prm, out, st, prof);
-    case 128: return batch_run_t<VT, 128>(g, bw, npairs, ps, pt, prm, out, st, prof);
-    case 256: return batch_run_t<VT, 256>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    case 16: return batch_run_t<VT, 16>(g, bw, npairs, ps, pt, prm, out, st, prof, compact);
+    case 32: return batch_run_t<VT, 32>(g, bw, npairs, ps, pt, prm, out, st, prof, compact);
+    case 64: return batch_run_t<VT, 64>(g, bw, npairs, ps, pt, prm, out, st, prof, compact);
+    case 128: return batch_run_t<VT, 128>(g, bw, npairs, ps, pt, prm, out, st, prof, compact);
+    case 256: return batch_run_t<VT, 256>(g, bw, npairs, ps, pt, prm, out, st, prof, compact);
   }
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
@@ -1231,19 +1326,16 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
                          grad_r ? grad_r + off : nullptr, bw->cw);
       std::pair<hipEvent_t, hipEvent_t> ev{};
       if (prof) {
-        ev = g->timer[2].next();
+        // chunks, column and edge ids of the upper entries, the accumulator
+        // read and written, the potential block read once
+        ev = g->timer[2].next(16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
+                              8.0 * B * (double)g->n + 8.0 * B);
         RD_HIP(hipEventRecord(ev.first, st));
       }
       hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
                          (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xp,
                          (const double *)bw->cw, bw->gacc);
-      if (prof) {
-        RD_HIP(hipEventRecord(ev.second, st));
-        // chunks, column and edge ids of the upper entries, the accumulator
-        // read and written, the potential block read once
-        g->timer[2].alg_bytes = 16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
-                                8.0 * B * (double)g->n + 8.0 * B;
-      }
+      if (prof) RD_HIP(hipEventRecord(ev.second, st));
     }
     RD_HIP(hipGetLastError());
   }
@@ -1424,10 +1516,12 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
         grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
       else
         grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
-    } else if (opt.precision == RD_F64) {
-      batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
     } else {
-      batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st, prof);
+      const bool compact = !(opt.flags & RD_NO_COMPACT);
+      if (opt.precision == RD_F64)
+        batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof, compact);
+      else
+        batch_dispatch<float>(g, bw, B, npairs, ds, dt, prm, dout, st, prof, compact);
     }
     if (!dp) {
       RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));

@@ -418,7 +418,9 @@ static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, int prv, int n
   VT *Y = (VT *)pw->U[nxt];
   std::pair<hipEvent_t, hipEvent_t> ev{};
   if (prof) {
-    ev = g->timer[1].next();
+    const double sv = sizeof(VT);
+    ev = g->timer[1].next((double)g->nnz * (4.0 + (g->unit ? 0.0 : sv)) + 4.0 * (g->n + 1) +
+                          3.0 * sv * g->n + (sv + 8.0) * g->n);
     RD_HIP(hipEventRecord(ev.first, st));
   }
   if (g->unit)
@@ -429,12 +431,7 @@ static void enqueue_iteration(rd_graph g, PlainWork *pw, int cur, int prv, int n
     hipLaunchKernelGGL((k_spmv<VT, true>), dim3(g->nblk), dim3(SPMV_THREADS), 0, st, g->blk_row,
                        g->blk_lanes, g->row_ptr, g->col, VecTraits<VT>::w(g),
                        VecTraits<VT>::invdeg(g), g->deg, Ucur, Uprev, Y, pw->part, pw->st);
-  if (prof) {
-    RD_HIP(hipEventRecord(ev.second, st));
-    const double sv = sizeof(VT);
-    g->timer[1].alg_bytes = (double)g->nnz * (4.0 + (g->unit ? 0.0 : sv)) + 4.0 * (g->n + 1) +
-                            3.0 * sv * g->n + (sv + 8.0) * g->n;
-  }
+  if (prof) RD_HIP(hipEventRecord(ev.second, st));
   hipLaunchKernelGGL(k_reduce_alpha, dim3(1), dim3(RED_THREADS), 0, st, pw->part, g->nblk, pw->st,
                      tr_alpha, tr_rhat);
   if (reorth == 0) enqueue_update<VT, 0>(g, pw, Ucur, Uprev, Y, st);

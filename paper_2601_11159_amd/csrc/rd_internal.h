@@ -76,11 +76,12 @@ struct BatchWork;
 // Event-timed launches of one kernel (RD_PROFILE).
 struct KernelTimer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-  size_t used = 0;       // events recorded in the current call
-  double total_ms = 0;   // resolved durations since the last read
+  std::vector<double> bytes;  // algorithmic bytes of each recorded launch
+  size_t used = 0;            // events recorded in the current call
+  double total_ms = 0;        // resolved durations since the last read
+  double total_bytes = 0;     // and their algorithmic bytes
   int64_t launches = 0;
-  double alg_bytes = 0;  // algorithmic bytes of one launch (last configuration)
-  std::pair<hipEvent_t, hipEvent_t> next();
+  std::pair<hipEvent_t, hipEvent_t> next(double alg_bytes);
   void resolve(size_t valid);  // after the stream is synchronised: count the first `valid` launches
   void release();
 };

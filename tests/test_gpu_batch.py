@@ -195,3 +195,34 @@ def test_reorth_gradient_matches_dense():
     G = rd.RDGraph(g.n, g.u, g.v, g.w)
     fwd, gw = G.grad_edges(s, t, None, 1e-12, _opts(block_width=32, reorth=2))
     assert np.linalg.norm(gw - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,width,eps,bar", [(rd.RD_F64, 64, 1e-10, 1e-8), (rd.RD_F32, 256, 1e-5, 1e-3)])
+def test_tail_compaction_matches_fixed_width(prec, width, eps, bar):
+    # uneven iteration counts (road-like grid): once the queue is empty the
+    # running columns move to narrower blocks, repeatedly down to 16
+    g = I.road_like(60, seed=9)
+    s, t = I.uniform_pairs(g.n, width + 40, seed=71)
+    t[3] = s[3]
+    mask = s != t
+    truth = np.zeros(len(s))
+    truth[mask] = D.rd_all(g, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v)
+    flags = rd.RD_GENERAL_PATH | rd.RD_PROFILE
+    G.kernel_stats(0)
+    comp = G.query_batch(s, t, eps, rd.rd_default_options(precision=prec, block_width=width, flags=flags))
+    _, n_c, bytes_c = G.kernel_stats(0)
+    fixed = G.query_batch(s, t, eps, rd.rd_default_options(precision=prec, block_width=width,
+                                                           flags=flags | rd.RD_NO_COMPACT))
+    _, n_f, bytes_f = G.kernel_stats(0)
+    assert np.all(comp["status"] == rd.RD_OK) and np.all(fixed["status"] == rd.RD_OK)
+    assert comp["r"][3] == 0.0
+    # narrower launches carry fewer algorithmic bytes: compaction happened
+    print(f"mean bytes per launch: {bytes_c:.4g} with compaction, {bytes_f:.4g} without")
+    assert bytes_c < bytes_f
+    for out in (comp, fixed):
+        err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+        assert err.max() <= bar, err.max()
+    assert np.all(np.abs(comp["iters"] - fixed["iters"]) <= 1)
+    if prec == rd.RD_F64:
+        np.testing.assert_allclose(comp["r"], fixed["r"], rtol=1e-11)
