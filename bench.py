@@ -184,9 +184,11 @@ def run_other(name, args):
                                                                          max_iters=100000))
         # batched FP64 (no refinement) on all pairs at the 1e-4 target
         log("batched FP32 unrefined (64 pairs) done")
-        o64 = rd.rd_default_options(precision=rd.RD_F64, block_width=64, max_iters=100000, flags=rd.RD_PROFILE)
+        w64 = G.tune_width(rd.RD_F64, len(s))
+        sched = G.batch_schedule()
+        o64 = rd.rd_default_options(precision=rd.RD_F64, block_width=w64, max_iters=100000, flags=rd.RD_PROFILE)
         b64q, b64out, b64roof, b64dt = _batch_rate(G, rd, s, t, 1e-4, o64)
-        log(f"batched FP64: {b64q:.3f} q/s")
+        log(f"batched FP64 (width {w64}, schedule {sched}): {b64q:.3f} q/s")
         # CPU oracle: a bounded number of iterations of one pair, scaled to a query
         from threadpoolctl import threadpool_limits
         from oracle import lanczos as LZ
@@ -199,8 +201,10 @@ def run_other(name, args):
         # path stops at ~1.2e-4 on this graph even with the FP64 energy refinement
         line = _line("queries/s", b64q, 1, 1, b64dt * 1e3, "f64",
                      {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": 1e-4,
-                      "path": "batched FP64 at eps 1e-4, width 64 (value); plain FP64 at 1e-4 on 8 pairs and "
-                              "batched FP32 + FP64 energy refinement at eps 1e-5 beside it"},
+                      "path": "batched FP64 at eps 1e-4 (value); plain FP64 at 1e-4 on 8 pairs and "
+                              "batched FP32 + FP64 energy refinement at eps 1e-5, width 64, beside it",
+                      "block_width": w64, "block_width_source": "autotuned",
+                      "row_schedule": dict(zip(("wave_nnz", "long_deg"), sched))},
                      plain_fp64={"value": round(plain_qps, 3), "unit": "queries/s", "mean_iters": float(pit.mean()),
                                  "roofline": proof},
                      speedup_batched_fp64_vs_plain_fp64=round(b64q / plain_qps, 2),
@@ -424,7 +428,9 @@ def main():
     # roofline of the dominant kernel
     avg_ms = k_ms / max(k_launches, 1)
     achieved = k_bytes / (avg_ms * 1e-3) / 1e9 if k_launches else None
-    traffic = load_traffic(args.workload + ("/reordered" if args.reorder else ""), width) if width else None
+    wave, long_deg = G.batch_schedule()
+    traffic = load_traffic(args.workload + ("/reordered" if args.reorder else "") + f"/w{wave}_l{long_deg}",
+                           width) if width else None
     roofline = {
         "kernel": "k_spmm_short (batched FP32 sparse product, rows of length <= 1024)",
         "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
@@ -465,6 +471,7 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "pairs": len(s), "eps_rel": EPS,
                    "precision": "FP32 vectors and sparse products, FP64 Lanczos scalars",
                    "block_width": width, "block_width_source": "fixed" if args.width else "autotuned",
+                   "row_schedule": dict(zip(("wave_nnz", "long_deg"), G.batch_schedule())),
                    "node_order": "decreasing degree (RD_REORDER)" if args.reorder else "as generated",
                    "mean_iters": round(float(iters.mean()), 3)},
         "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,

@@ -172,14 +172,25 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
                          double eps, const rd_options *o, rd_result *out);
 
 /*
- * The block width rd_query_batch uses when rd_options.block_width is 0: the
- * width among 32, 64, 128, 256 (not wider than needed for npairs) whose
- * sparse product takes the least time per column on this graph, measured on
- * first use with HIP events on `stream` (NULL: the handle's stream) and kept
- * on the handle; with the environment variable RD_AUTOTUNE_CACHE naming a
- * file, choices are also read from and appended to that file.
+ * The block width rd_query_batch uses when rd_options.block_width is 0, and
+ * the row-bin schedule of its sparse product. First the width among 32, 64,
+ * 128, 256 (not wider than needed for npairs) whose sparse product takes the
+ * least time per column on this graph; then, at that width, the schedule
+ * (entries per wavefront work item: 128, 256 or 512; rows longer than 512,
+ * 1024 or 2048 entries get a workgroup of their own) with the least time.
+ * Measured on first use with HIP events on `stream` (NULL: the handle's
+ * stream) and kept on the handle per precision; with the environment variable
+ * RD_AUTOTUNE_CACHE naming a file, choices are also read from and appended to
+ * that file. The chosen schedule stays in effect for later calls, also with
+ * an explicit block_width.
  */
 rd_status rd_tune_width(rd_graph g, int32_t precision, int32_t npairs, void *stream, int32_t *width);
+
+/* The row-bin schedule currently in effect for rd_query_batch on g: entries
+ * per wavefront work item and the row length above which a row gets a
+ * workgroup of its own (defaults 256 and 1024 until the autotuner runs).
+ * Either pointer may be NULL. */
+rd_status rd_batch_schedule(rd_graph g, int32_t *wave_nnz, int32_t *long_deg);
 
 /*
  * Edge-weight gradient of L = sum_p grad_r[p] r(s_p, t_p):

@@ -34,6 +34,7 @@ namespace {
 
 constexpr int SHORT_THREADS = 256;
 constexpr int LONG_THREADS = 1024;
+// default row-bin schedule (the autotuner may choose another per graph)
 constexpr int LONG_DEG = 1024;   // rows longer than this go to the split-row kernel
 constexpr int WAVE_NNZ = 256;    // adjacency entries per wave work item (short rows)
 constexpr int COL_THREADS = 256;
@@ -105,7 +106,7 @@ __device__ __forceinline__ void block_column_partials(double (&apart)[VEC], doub
   __syncthreads();
 }
 
-// Rows of length <= LONG_DEG. Wave work items are contiguous row ranges of
+// Rows of length <= long_deg. Wave work items are contiguous row ranges of
 // bounded adjacency length; items are dealt to wavefronts round-robin (a fixed
 // assignment, so the partial sums do not depend on timing).
 template <typename VT, int B, bool WEIGHTED>
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
     const int32_t *__restrict__ col, const VT *__restrict__ w, const VT *__restrict__ invdeg,
     const double *__restrict__ deg, const VT *__restrict__ Ucur, const VT *__restrict__ Uprev,
     VT *__restrict__ Y, const ColCtrl *__restrict__ ctrl, double *__restrict__ part, int32_t ldp,
-    const int32_t *__restrict__ active) {
+    const int32_t *__restrict__ active, int32_t long_deg) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
     const int32_t rb = witem_row[2 * it], re = witem_row[2 * it + 1];
     for (int32_t r = rb + sub; r < re; r += S::RPW) {
       const int32_t pb = row_ptr[r], pe = row_ptr[r + 1];
-      if (pe - pb > LONG_DEG) continue;
+      if (pe - pb > long_deg) continue;
       // the row's own operands, loaded ahead of the gathers (narrow lanes only:
       // wider ones lose more to occupancy than they gain)
       V up, uc;
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_spmm_short(
   block_column_partials<B, VEC>(apart, sm, part, ldp, blockIdx.x);
 }
 
-// Rows longer than LONG_DEG: one block per row, entries split over all
+// Rows longer than long_deg: one block per row, entries split over all
 // sub-rows of the block and combined in LDS in a fixed order.
 template <typename VT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
@@ -911,7 +912,11 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 // ---------------------------------------------------------------------------
 
 struct BatchWork {
-  // schedule (independent of B and precision)
+  // row-bin schedule (independent of B and precision): wave work items of at
+  // most wave_nnz entries over rows of at most long_deg entries, longer rows
+  // listed separately
+  int32_t wave_nnz = 0, long_deg = 0;
+  std::vector<int32_t> rp_host;  // row offsets, kept to rebuild the schedule
   int32_t nwi = 0, nlong = 0;
   int64_t nnz_short = 0;  // adjacency entries of rows handled by k_spmm_short
   int32_t n_short = 0;    // rows handled by k_spmm_short
@@ -922,8 +927,9 @@ struct BatchWork {
   size_t vec_bytes = 0;
   void *X[3] = {nullptr, nullptr, nullptr};  // q_{i-1}, q_i and the new vector rotate
   int32_t Bcap = 0;
-  double *part = nullptr;  // [Bcap][ldp]
-  int32_t ldp = 0;
+  double *part = nullptr;  // [Bcap][ldp_cap]
+  int32_t ldp = 0;      // partial slots per column of the current schedule
+  int32_t ldp_cap = 0;  // slots the partial buffers were sized for
   double *colsum = nullptr;  // [Bcap]
   double *rpart = nullptr;   // re-orthogonalisation partials [3][Bcap][ldp]
   double *rsum = nullptr;    // [3 * 256]
@@ -938,8 +944,9 @@ struct BatchWork {
   int32_t *qstate_host = nullptr;  // pinned
   int32_t *flag = nullptr;
   int32_t *cmap = nullptr;  // [128] source columns of a compaction
-  // autotune cache: chosen width per precision
+  // autotune cache: chosen width and schedule per precision
   int32_t tuned[2] = {0, 0};
+  int32_t tuned_wave[2] = {0, 0}, tuned_long[2] = {0, 0};
 };
 
 void batch_free(rd_graph g) {
@@ -966,19 +973,17 @@ void batch_free(rd_graph g) {
   g->batch = nullptr;
 }
 
-static BatchWork *batch_get(rd_graph g) {
-  if (g->batch) return g->batch;
-  BatchWork *bw = new BatchWork();
-  g->batch = bw;
-  std::vector<int32_t> rp(g->n + 1);
-  RD_HIP(hipMemcpy(rp.data(), g->row_ptr, (g->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+// (Re)build the row-bin schedule: [begin, end) ranges of consecutive rows of at
+// most long_deg entries holding at most wave_nnz entries (or one row), and the
+// list of longer rows.
+static void build_schedule(rd_graph g, BatchWork *bw, int32_t wave_nnz, int32_t long_deg) {
+  if (bw->witem_row && wave_nnz == bw->wave_nnz && long_deg == bw->long_deg) return;
+  const std::vector<int32_t> &rp = bw->rp_host;
   std::vector<int32_t> items, longs;
-  items.reserve(g->nnz / WAVE_NNZ + 16);
-  // items: [begin, end) ranges of consecutive short rows holding at most
-  // WAVE_NNZ entries (or one row); long rows are listed separately
+  items.reserve(g->nnz / wave_nnz + 16);
   int32_t r = 0;
   while (r < g->n) {
-    if (rp[r + 1] - rp[r] > LONG_DEG) {
+    if (rp[r + 1] - rp[r] > long_deg) {
       longs.push_back(r);
       ++r;
       continue;
@@ -987,20 +992,24 @@ static BatchWork *batch_get(rd_graph g) {
     int64_t acc = 0;
     while (r < g->n) {
       const int32_t len = rp[r + 1] - rp[r];
-      if (len > LONG_DEG || (acc > 0 && acc + len > WAVE_NNZ)) break;
+      if (len > long_deg || (acc > 0 && acc + len > wave_nnz)) break;
       acc += len;
       ++r;
     }
     items.push_back(begin);
     items.push_back(r);
   }
+  dev_free(bw->witem_row);
+  dev_free(bw->long_rows);
+  bw->witem_row = bw->long_rows = nullptr;
   bw->nwi = (int32_t)items.size() / 2;
   bw->n_short = g->n - (int32_t)longs.size();
   bw->nnz_short = g->nnz;
   for (int32_t lr : longs) bw->nnz_short -= rp[lr + 1] - rp[lr];
   bw->nlong = (int32_t)longs.size();
-  bw->witem_row = (int32_t *)dev_alloc(items.size() * sizeof(int32_t));
-  RD_HIP(hipMemcpy(bw->witem_row, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  bw->witem_row = (int32_t *)dev_alloc(std::max<size_t>(2, items.size()) * sizeof(int32_t));
+  if (!items.empty())
+    RD_HIP(hipMemcpy(bw->witem_row, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   bw->long_rows = (int32_t *)dev_alloc(std::max<size_t>(1, longs.size()) * sizeof(int32_t));
   if (!longs.empty())
     RD_HIP(hipMemcpy(bw->long_rows, longs.data(), longs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -1012,6 +1021,17 @@ static BatchWork *batch_get(rd_graph g) {
   bw->grid_short = std::max(1, std::min<int32_t>(cus * 8, (bw->nwi + 3) / 4));
   bw->grid_upd = std::max(1, std::min<int32_t>(cus * 8, cdiv(g->n, 64)));
   bw->ldp = std::max(bw->grid_short + bw->nlong, bw->grid_upd);
+  bw->wave_nnz = wave_nnz;
+  bw->long_deg = long_deg;
+}
+
+static BatchWork *batch_get(rd_graph g) {
+  if (g->batch) return g->batch;
+  BatchWork *bw = new BatchWork();
+  g->batch = bw;
+  bw->rp_host.resize((size_t)g->n + 1);
+  RD_HIP(hipMemcpy(bw->rp_host.data(), g->row_ptr, (g->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  build_schedule(g, bw, WAVE_NNZ, LONG_DEG);
   bw->st = (LzState *)dev_alloc(256 * sizeof(LzState));
   bw->ctrl = (ColCtrl *)dev_alloc(256 * sizeof(ColCtrl));
   bw->colsum = (double *)dev_alloc(256 * sizeof(double));
@@ -1033,18 +1053,19 @@ static void batch_reserve(rd_graph g, BatchWork *bw, int32_t B, size_t elem) {
     for (void *&x : bw->X) x = dev_alloc(need);
     bw->vec_bytes = need;
   }
-  if (B > bw->Bcap) {
+  if (B > bw->Bcap || bw->ldp > bw->ldp_cap) {
     dev_free(bw->part);
     dev_free(bw->rpart);
     bw->part = bw->rpart = nullptr;
-    bw->part = (double *)dev_alloc((size_t)B * bw->ldp * sizeof(double));
-    bw->Bcap = B;
+    bw->Bcap = std::max(B, bw->Bcap);
+    bw->ldp_cap = std::max(bw->ldp, bw->ldp_cap);
+    bw->part = (double *)dev_alloc((size_t)bw->Bcap * bw->ldp_cap * sizeof(double));
   }
 }
 
 // Partial and column-sum buffers of the re-orthogonalisation (on first use).
 static void reorth_reserve(BatchWork *bw) {
-  if (!bw->rpart) bw->rpart = (double *)dev_alloc(3 * (size_t)bw->Bcap * bw->ldp * sizeof(double));
+  if (!bw->rpart) bw->rpart = (double *)dev_alloc(3 * (size_t)bw->Bcap * bw->ldp_cap * sizeof(double));
   if (!bw->rsum) bw->rsum = (double *)dev_alloc(3 * 256 * sizeof(double));
 }
 
@@ -1070,7 +1091,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Upr
   }
   hipLaunchKernelGGL((k_spmm_short<VT, B, WEIGHTED>), dim3(bw->grid_short), dim3(SHORT_THREADS), 0, st,
                      bw->nwi, bw->witem_row, g->row_ptr, g->col, w, invdeg, g->deg, Ucur, Uprev, Y,
-                     bw->ctrl, bw->part, bw->ldp, active);
+                     bw->ctrl, bw->part, bw->ldp, active, bw->long_deg);
   if (prof) RD_HIP(hipEventRecord(ev.second, st));
   if (bw->nlong > 0)
     hipLaunchKernelGGL((k_spmm_long<VT, B, WEIGHTED>), dim3(bw->nlong), dim3(LONG_THREADS), 0, st,
@@ -1415,41 +1436,72 @@ static std::string tune_key(rd_graph g, int prec) {
   return k.str();
 }
 
-// Width with the least sparse-product time per column among the candidates
-// that fit the number of pairs; remembered per handle and, when the
-// RD_AUTOTUNE_CACHE environment variable names a file, across processes.
+// Block width and row-bin schedule with the least sparse-product time per
+// column: first the width (candidates that fit the number of pairs) under the
+// default schedule, then the schedule at that width (entries per wave work
+// item 128/256/512, long-row threshold 512/1024/2048). Remembered per handle
+// and precision and, when the environment variable RD_AUTOTUNE_CACHE names a
+// file, read from and appended to that file. Leaves the chosen schedule
+// built; returns the width.
 static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npairs, hipStream_t st) {
-  if (bw->tuned[prec]) return bw->tuned[prec];
-  const char *path = std::getenv("RD_AUTOTUNE_CACHE");
-  const std::string key = tune_key(g, prec);
-  if (path) {
-    std::ifstream f(path);
-    std::string line;
-    while (std::getline(f, line)) {
-      const auto sp = line.rfind(' ');
-      if (sp != std::string::npos && line.substr(0, sp) == key) {
-        const int32_t B = std::atoi(line.c_str() + sp + 1);
-        if (B == 16 || B == 32 || B == 64 || B == 128 || B == 256) return bw->tuned[prec] = B;
+  auto valid_width = [](int32_t B) { return B == 16 || B == 32 || B == 64 || B == 128 || B == 256; };
+  if (!bw->tuned[prec]) {
+    const char *path = std::getenv("RD_AUTOTUNE_CACHE");
+    const std::string key = tune_key(g, prec);
+    if (path) {
+      std::ifstream f(path);
+      std::string line;
+      while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string k;
+        int32_t B = 0, wv = 0, ld = 0;
+        if ((in >> k >> B >> wv >> ld) && k == key && valid_width(B) && wv >= 32 && ld >= 64) {
+          bw->tuned[prec] = B;
+          bw->tuned_wave[prec] = wv;
+          bw->tuned_long[prec] = ld;
+        }
+      }
+    }
+    if (!bw->tuned[prec]) {
+      auto probe = [&](int32_t B) {
+        return prec == RD_F64 ? probe_dispatch<double>(g, bw, B, st) : probe_dispatch<float>(g, bw, B, st);
+      };
+      build_schedule(g, bw, WAVE_NNZ, LONG_DEG);
+      int32_t best = 0;
+      double best_t = 1e300;
+      for (int32_t B : {32, 64, 128, 256}) {
+        if (B > 32 && B / 2 >= npairs) break;  // wider than the work: no gain
+        const double per_col = probe(B) / B;
+        if (per_col < best_t) {
+          best_t = per_col;
+          best = B;
+        }
+      }
+      int32_t best_wave = WAVE_NNZ, best_long = LONG_DEG;
+      double best_s = probe(best);  // the default schedule, measured again next to the others
+      for (int32_t wv : {128, 256, 512}) {
+        for (int32_t ld : {512, 1024, 2048}) {
+          if (wv == WAVE_NNZ && ld == LONG_DEG) continue;
+          build_schedule(g, bw, wv, ld);
+          const double t = probe(best);
+          if (t < best_s) {
+            best_s = t;
+            best_wave = wv;
+            best_long = ld;
+          }
+        }
+      }
+      bw->tuned[prec] = best;
+      bw->tuned_wave[prec] = best_wave;
+      bw->tuned_long[prec] = best_long;
+      if (path) {
+        std::ofstream f(path, std::ios::app);
+        f << key << " " << best << " " << best_wave << " " << best_long << "\n";
       }
     }
   }
-  int32_t best = 0;
-  double best_t = 1e300;
-  for (int32_t B : {32, 64, 128, 256}) {
-    if (B > 32 && B / 2 >= npairs) break;  // wider than the work: no gain
-    const float ms = prec == RD_F64 ? probe_dispatch<double>(g, bw, B, st) : probe_dispatch<float>(g, bw, B, st);
-    const double per_col = ms / B;
-    if (per_col < best_t) {
-      best_t = per_col;
-      best = B;
-    }
-  }
-  bw->tuned[prec] = best;
-  if (path) {
-    std::ofstream f(path, std::ios::app);
-    f << key << " " << best << "\n";
-  }
-  return best;
+  build_schedule(g, bw, bw->tuned_wave[prec], bw->tuned_long[prec]);
+  return bw->tuned[prec];
 }
 
 extern "C" {
@@ -1619,6 +1671,21 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
 }
 
 }  // extern "C"
+
+extern "C" rd_status rd_batch_schedule(rd_graph g, int32_t *wave_nnz, int32_t *long_deg) {
+  if (!g) return RD_E_ARG;
+  try {
+    g->err.clear();
+    RD_HIP(hipSetDevice(g->device));
+    BatchWork *bw = batch_get(g);
+    if (wave_nnz) *wave_nnz = bw->wave_nnz;
+    if (long_deg) *long_deg = bw->long_deg;
+    return RD_OK;
+  } catch (const RdError &e) {
+    g->err = e.msg;
+    return e.code;
+  }
+}
 
 extern "C" rd_status rd_tune_width(rd_graph g, int32_t precision, int32_t npairs, void *stream,
                                    int32_t *width) {

@@ -37,7 +37,7 @@ RD_F32 = 1
 EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
-    "rd_last_error", "rd_kernel_stats", "rd_tune_width",
+    "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule",
 ]
 
 
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
     lib.rd_tune_width.restype = ctypes.c_int
+    lib.rd_batch_schedule.argtypes = [vp, P(i32), P(i32)]
+    lib.rd_batch_schedule.restype = ctypes.c_int
     lib.rd_kernel_stats.argtypes = [vp, i32, P(dbl), P(i64), P(dbl)]
     lib.rd_kernel_stats.restype = ctypes.c_int
     lib.rd_free_graph.argtypes = [vp]
@@ -227,6 +229,15 @@ class RDGraph:
         if rc != RD_OK:
             self._raise(rc, "rd_tune_width")
         return w.value
+
+    def batch_schedule(self):
+        """(entries per wavefront work item, long-row threshold) of the
+        batched product's row-bin schedule currently in effect."""
+        wv, ld = ctypes.c_int32(), ctypes.c_int32()
+        rc = load().rd_batch_schedule(self._h, ctypes.byref(wv), ctypes.byref(ld))
+        if rc != RD_OK:
+            self._raise(rc, "rd_batch_schedule")
+        return wv.value, ld.value
 
     def kernel_stats(self, which: int):
         """(total ms, launches, algorithmic bytes per launch) of the sparse

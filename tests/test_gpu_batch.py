@@ -151,15 +151,29 @@ def test_batch_argument_errors():
     assert len(G.query_batch(np.zeros(0, np.int32), np.zeros(0, np.int32), 1e-6)) == 0
 
 
-def test_autotuned_width_runs():
+def test_autotuned_width_and_schedule(tmp_path, monkeypatch):
+    # rows longer than 512 entries exist, so the long-row threshold matters
     g = I.chung_lu(50000, 2.3, 32, seed=4)
+    assert np.bincount(np.r_[g.u, g.v]).max() > 512
     s, t = I.uniform_pairs(g.n, 300, seed=2)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RD_AUTOTUNE_CACHE", str(cache))
     G = rd.RDGraph(g.n, g.u, g.v)
+    assert G.batch_schedule() == (256, 1024)  # the default before tuning
+    width = G.tune_width(rd.RD_F32, len(s))
+    wave, long_deg = G.batch_schedule()
+    assert width in (32, 64, 128, 256)
+    assert wave in (128, 256, 512) and long_deg in (512, 1024, 2048)
     out = G.query_batch(s, t, 1e-4, _opts(precision=rd.RD_F32))
     A, d = LZ.normalized_adjacency(g)
     for p in range(0, 300, 50):
         run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-10, A=A, d=d)
         assert abs(out["r"][p] - run.r) / run.r <= 1e-4
+    # a new handle on the same graph reads the choice back from the cache file
+    assert cache.read_text().split()[-3:] == [str(width), str(wave), str(long_deg)]
+    G2 = rd.RDGraph(g.n, g.u, g.v)
+    assert G2.tune_width(rd.RD_F32, len(s)) == width
+    assert G2.batch_schedule() == (wave, long_deg)
 
 
 @pytest.mark.parametrize("ro", [1, 2])
