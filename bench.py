@@ -92,7 +92,7 @@ def _batch_rate(G, rd, s, t, eps, opts, steps=1):
     dt = (time.time() - t0) / steps
     ms, n, b = G.kernel_stats(0)
     avg = ms / max(n, 1)
-    roof = {"kernel": "k_spmm_short (batched sparse product, rows of length <= 1024)", "bound": "hbm",
+    roof = {"kernel": "k_spmm_short (batched sparse product over the short rows)", "bound": "hbm",
             "achieved": round(b / (avg * 1e-3) / 1e9, 1) if n else None, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if n else None,
             "traffic": None, "avg_launch_ms": round(avg, 4), "launches": n, "alg_bytes_per_launch": b}
@@ -275,7 +275,7 @@ def kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2601_11159_amd", "csrc", "lanczos_batch.hip")
     src = open(p).read()
     a = src.index("// Fold the per-lane column partials")
-    b = src.index("// Rows longer than LONG_DEG")
+    b = src.index("// Rows longer than long_deg")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -432,7 +432,7 @@ def main():
     traffic = load_traffic(args.workload + ("/reordered" if args.reorder else "") + f"/w{wave}_l{long_deg}",
                            width) if width else None
     roofline = {
-        "kernel": "k_spmm_short (batched FP32 sparse product, rows of length <= 1024)",
+        "kernel": "k_spmm_short (batched FP32 sparse product over the short rows)",
         "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": k_launches,

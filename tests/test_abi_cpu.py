@@ -84,3 +84,20 @@ def test_lognormal_weights():
     lw = np.log(w.astype(np.float64))
     assert abs(lw.mean()) < 0.01 and abs(lw.std() - 1.0) < 0.01
     assert np.array_equal(w, I.lognormal_weights(200000, 0.0, 1.0, seed=5))
+
+
+def test_bench_traffic_lookup_hashes_the_kernel_source():
+    # the committed counter summary is keyed by workload, schedule and width
+    # and is used only while the kernel source is unchanged
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    import json
+    d = json.load(open(os.path.join(ROOT, "profiles", "spmm_short_traffic.json")))
+    for key, e in d.items():
+        workload, width = key.rsplit("/B", 1)
+        got = bench.load_traffic(workload, int(width))
+        assert (got is not None) == (e["source_hash"] == h)
