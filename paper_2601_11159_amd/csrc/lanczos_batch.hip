@@ -41,7 +41,21 @@ constexpr int COL_THREADS = 256;
 
 // COL_FINAL: the run stopped at this iteration; only the potential is updated
 // (gradient mode), then the column is idle.
-enum : int32_t { COL_RUN = 0, COL_REFILL = 1, COL_IDLE = 2, COL_FINAL = 3 };
+// Gradient mode with refill ("harvest"): a finished column's potential is
+// copied into slot hslot of the block of finished potentials (COL_FINAL with
+// hslot >= 0, or COL_HARVEST for a potential already complete); COL_PENDING
+// waits for a free slot. The slot is refilled after its potential is copied.
+enum : int32_t {
+  COL_RUN = 0,
+  COL_REFILL = 1,
+  COL_IDLE = 2,
+  COL_FINAL = 3,
+  COL_HARVEST = 4,
+  COL_PENDING = 5
+};
+
+// gradient handling of a batched run
+enum : int32_t { GRAD_NONE = 0, GRAD_GROUPS = 1, GRAD_HARVEST = 2 };
 
 struct ColCtrl {
   double sig;   // q = sig * U_cur[:, j]
@@ -58,7 +72,7 @@ struct ColCtrl {
   int32_t s, t;
   int32_t prev_sparse;  // the previous vector is q_1 (vs at s, vt at t, zero elsewhere)
   int32_t upd_sparse;   // the same, for the update of the current iteration
-  int32_t pad;
+  int32_t hslot;        // harvest slot of the finished potential (-1: none)
 };
 
 template <typename VT, int N>
@@ -325,6 +339,8 @@ struct RunParams {
   int32_t max_iters, fixed_k, delay, err_mode;
   int32_t npairs;
   int32_t reorth;
+  int32_t gmode;          // GRAD_NONE, GRAD_GROUPS or GRAD_HARVEST
+  const double *grad_r;   // harvest mode: weight of each pair (nullptr: ones)
 };
 
 __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
@@ -337,8 +353,12 @@ __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
 }
 
 // Scalar step for every column after alpha, then retirement and refill in
-// column order (one block; thread 0 pops the pair queue serially so the
-// assignment of pairs to slots is deterministic).
+// column order (one block; thread 0 pops the pair queue and hands out harvest
+// slots serially, so the assignment of pairs and slots is deterministic).
+// grad: GRAD_NONE, GRAD_GROUPS (no refill; a stopped run adds its last
+// potential term, then idles) or GRAD_HARVEST (a stopped run adds its last
+// term and its potential is copied to a harvest slot, with weight
+// cw[slot] = grad_r[pair] * c, before the column is refilled).
 __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict__ st,
                                                  ColCtrl *__restrict__ ctrl,
                                                  const double *__restrict__ alpha, RunParams prm,
@@ -346,18 +366,26 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
                                                  const int32_t *__restrict__ pt,
                                                  const double *__restrict__ deg,
                                                  rd_result *__restrict__ out,
-                                                 int32_t *__restrict__ qstate, int32_t grad) {
-  // qstate: [0] next pair, [1] active columns, [2] iterations with work, [3] constant 1.
+                                                 int32_t *__restrict__ qstate, int32_t grad,
+                                                 const double *__restrict__ grad_r, double *__restrict__ cw) {
+  // qstate: [0] next pair, [1] active columns, [2] iterations with work, [3] constant 1,
+  // [4] harvest slots in use.
   // Every call but the first (which fills the slots) returns once no column is active.
   if (qstate[1] == 0 && qstate[2] > 0) return;
   __shared__ int32_t need[256];
+  __shared__ int32_t wants[256];
   __shared__ int32_t newpair[256];
+  __shared__ int32_t slot[256];
   const int j = threadIdx.x;
+  const bool harvest = grad == GRAD_HARVEST;
   LzState S;
   double pa = 0.0, xb = 0.0;
-  bool advanced = false;
+  bool advanced = false, fin = false, pending = false;
   if (j < B) {
     S = st[j];
+    const ColCtrl &pc = ctrl[j];
+    // harvest mode: a finished potential still waiting for a slot
+    pending = harvest && (pc.mode == COL_PENDING || (pc.mode == COL_FINAL && pc.hslot < 0));
     const bool was_running = S.status == LZ_RUNNING;
     const double delta_prev = S.delta, beta_i = S.beta;
     const int32_t k_prev = S.k;
@@ -371,14 +399,23 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       pa = S.k > 1 ? beta_i / delta_prev : 0.0;
       xb = S.omega / S.delta;
     }
-    const bool fin = S.status == LZ_DONE || S.status == LZ_NOT_CONVERGED || S.status == LZ_BREAKDOWN;
+    fin = S.status == LZ_DONE || S.status == LZ_NOT_CONVERGED || S.status == LZ_BREAKDOWN;
     if (fin) write_result(out, S);
-    need[j] = (fin || S.status == LZ_IDLE) ? 1 : 0;
+    if (harvest) {
+      wants[j] = (fin || pending) ? 1 : 0;
+      need[j] = (!fin && !pending && S.status == LZ_IDLE) ? 1 : 0;
+    } else {
+      wants[j] = 0;
+      need[j] = (fin || S.status == LZ_IDLE) ? 1 : 0;
+    }
   }
   __syncthreads();
   if (j == 0) {
     int32_t head = qstate[0];
+    int32_t used = qstate[4];
     for (int c = 0; c < B; ++c) {
+      slot[c] = -1;
+      if (wants[c] && used < B) slot[c] = used++;
       newpair[c] = -2;
       if (!need[c]) continue;
       int32_t idx = -1;
@@ -394,13 +431,29 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       newpair[c] = idx;
     }
     qstate[0] = head;
+    qstate[4] = used;
   }
   __syncthreads();
   int32_t active = 0;
   if (j < B) {
     ColCtrl cc = ctrl[j];
     const int32_t np = newpair[j];
-    if (np >= 0) {
+    if (harvest && (fin || pending)) {
+      // finished: last potential term (if this iteration added one), then the
+      // copy to a harvest slot, or wait for one
+      const bool final_term = fin && advanced && S.status != LZ_BREAKDOWN;
+      const int32_t sl = slot[j];
+      if (sl >= 0) cw[sl] = (grad_r ? grad_r[S.pair] : 1.0) * S.c;
+      S.status = LZ_IDLE;
+      cc.mode = final_term ? COL_FINAL : (sl >= 0 ? COL_HARVEST : COL_PENDING);
+      cc.hslot = sl;
+      cc.pa = pa;
+      cc.xb = xb;
+      cc.pc = 0.0;
+      cc.coef = 0.0;
+      cc.upd_sparse = 0;
+      active = 1;
+    } else if (np >= 0) {
       const int32_t s = ps[np], t = pt[np];
       const double c = 1.0 / deg[s] + 1.0 / deg[t];
       state_start(S, s, t, c, prm.tol, prm.max_iters, prm.fixed_k, prm.delay, prm.err_mode, np);
@@ -413,15 +466,17 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       cc.vt = -rc / deg[t];
       cc.prev_sparse = 0;
       cc.upd_sparse = 0;
+      cc.hslot = -1;
       cc.s = s;
       cc.t = t;
       active = 1;
     } else if (np == -1) {
       // a run that stopped at this iteration still adds its last term to the
-      // potential (gradient mode); the column is idle afterwards
-      const bool final_term = grad && advanced && S.status != LZ_BREAKDOWN;
+      // potential (gradient groups); the column is idle afterwards
+      const bool final_term = grad == GRAD_GROUPS && advanced && S.status != LZ_BREAKDOWN;
       S.status = LZ_IDLE;
       cc.mode = final_term ? COL_FINAL : COL_IDLE;
+      cc.hslot = -1;
       cc.pa = pa;
       cc.xb = xb;
       if (final_term) active = 1;
@@ -469,7 +524,8 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
                                                           double *__restrict__ part, int32_t ldp,
                                                           const int32_t *__restrict__ active,
                                                           double *__restrict__ P, double *__restrict__ X,
-                                                          int32_t ro, double *__restrict__ rpart) {
+                                                          int32_t ro, double *__restrict__ rpart,
+                                                          double *__restrict__ Xf) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -479,7 +535,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
   const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
   VT coef[VEC], vs[VEC], vt[VEC], sig[VEC];
   double pa[VEC], xb[VEC];
-  int32_t mode[VEC], cs[VEC], ct[VEC];
+  int32_t mode[VEC], cs[VEC], ct[VEC], hs[VEC];
   bool psp[VEC];
   bool pot = false;
   double acc[VEC], a1[VEC], ac[VEC], ap[VEC];
@@ -496,8 +552,10 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     cs[v] = cc.s;
     ct[v] = cc.t;
     psp[v] = cc.upd_sparse != 0;
+    hs[v] = cc.hslot;
     acc[v] = a1[v] = ac[v] = ap[v] = 0.0;
-    pot = pot || mode[v] == COL_RUN || mode[v] == COL_FINAL;
+    pot = pot || mode[v] == COL_RUN || mode[v] == COL_FINAL || mode[v] == COL_HARVEST ||
+          mode[v] == COL_REFILL;
   }
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
@@ -539,10 +597,18 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
             const double p = (double)sig[v] * (double)uc.v[v] + pa[v] * pv.v[v];
             pv.v[v] = p;
             xv.v[v] += xb[v] * p;
+          } else if (mode[v] == COL_REFILL) {
+            pv.v[v] = 0.0;  // a new run's potential starts from zero
+            xv.v[v] = 0.0;
           }
         }
         vstore<double, VEC>(P + (size_t)r * B + c0, pv);
         vstore<double, VEC>(X + (size_t)r * B + c0, xv);
+        // a finished potential goes to its harvest slot
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if ((mode[v] == COL_FINAL || mode[v] == COL_HARVEST) && hs[v] >= 0)
+            Xf[(size_t)r * B + hs[v]] = xv.v[v];
       }
     }
   }
@@ -648,11 +714,13 @@ __device__ __forceinline__ double segment_sum(double x) {
 //   gacc[e] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair.
 // One row segment (LPR lanes over the columns) per edge chunk; four edges in
 // flight per segment; FP64 sums in a fixed order.
+// gate != nullptr: run only when *gate == B (a full block of harvested potentials).
 template <int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
     int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
     const int32_t *__restrict__ eid, const double *__restrict__ X, const double *__restrict__ cw,
-    double *__restrict__ gacc) {
+    double *__restrict__ gacc, const int32_t *__restrict__ gate) {
+  if (gate && *gate != B) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   using XV = VecN<double, VEC>;
@@ -700,6 +768,17 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
       if (cl == 0) gacc[eid[p]] -= a;
     }
   }
+}
+
+// After the edge pass of a full harvest block: the slots are free again and
+// their weights zero (so a final pass over a partly filled block counts only
+// the slots in use).
+__global__ void k_harvest_reset(int32_t B, int32_t *__restrict__ qstate, double *__restrict__ cw) {
+  if (qstate[4] != B) return;
+  __syncthreads();
+  for (int j = threadIdx.x; j < B; j += blockDim.x) cw[j] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) qstate[4] = 0;
 }
 
 // Per-column energy of the accumulated potentials, sum_e w_e (X[u,p] - X[v,p])^2
@@ -762,14 +841,6 @@ __global__ void k_refine_out(const LzState *__restrict__ st, const double *__res
   if (S.pair < 0) return;
   const double xs = X[(size_t)S.s * B + j], xt = X[(size_t)S.t * B + j];
   out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
-}
-
-__global__ void k_grad_weights(int32_t B, const LzState *__restrict__ st,
-                               const double *__restrict__ grad_r, double *__restrict__ cw) {
-  const int j = threadIdx.x;
-  if (j >= B) return;
-  const LzState &S = st[j];
-  cw[j] = S.pair >= 0 ? (grad_r ? grad_r[S.pair] : 1.0) * S.c : 0.0;
 }
 
 __global__ void k_to_float(int64_t m, const double *__restrict__ a, float *__restrict__ b) {
@@ -867,16 +938,11 @@ __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__re
     state_start(S, 0, 0, 0.0, 0.0, 0, 0, 4, 0, -1);
     S.status = LZ_IDLE;
     st[j] = S;
-    ColCtrl cc;
-    cc.sig = 0.0;
-    cc.pc = 0.0;
-    cc.coef = 0.0;
-    cc.vs = 0.0;
-    cc.vt = 0.0;
+    ColCtrl cc{};
     cc.mode = COL_IDLE;
     cc.s = -1;
     cc.t = -1;
-    cc.prev_sparse = 0;
+    cc.hslot = -1;
     ctrl[j] = cc;
   }
   if (j == 0) {
@@ -884,6 +950,7 @@ __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__re
     qstate[1] = 0;
     qstate[2] = 0;
     qstate[3] = 1;
+    qstate[4] = 0;
   }
 }
 
@@ -935,12 +1002,14 @@ struct BatchWork {
   double *rsum = nullptr;    // [3 * 256]
   // gradient mode: search directions and potentials (n x B each), edge accumulator
   void *P = nullptr, *Xp = nullptr;
+  void *Xf = nullptr;  // gradient harvest mode: n x B finished potentials (FP64)
   size_t pot_bytes = 0;
   double *gacc = nullptr;  // [m]
   double *cw = nullptr;    // [256]
   LzState *st = nullptr;
   ColCtrl *ctrl = nullptr;
-  int32_t *qstate = nullptr;       // [4]: queue head, active columns, working iterations, 1
+  int32_t *qstate = nullptr;       // [8]: queue head, active columns, working iterations, 1,
+                                   // harvest slots in use
   int32_t *qstate_host = nullptr;  // pinned
   int32_t *flag = nullptr;
   int32_t *cmap = nullptr;  // [128] source columns of a compaction
@@ -961,6 +1030,7 @@ void batch_free(rd_graph g) {
   dev_free(bw->rsum);
   dev_free(bw->P);
   dev_free(bw->Xp);
+  dev_free(bw->Xf);
   dev_free(bw->gacc);
   dev_free(bw->cw);
   dev_free(bw->st);
@@ -1035,7 +1105,7 @@ static BatchWork *batch_get(rd_graph g) {
   bw->st = (LzState *)dev_alloc(256 * sizeof(LzState));
   bw->ctrl = (ColCtrl *)dev_alloc(256 * sizeof(ColCtrl));
   bw->colsum = (double *)dev_alloc(256 * sizeof(double));
-  bw->qstate = (int32_t *)dev_alloc(4 * sizeof(int32_t));
+  bw->qstate = (int32_t *)dev_alloc(8 * sizeof(int32_t));
   bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
   bw->cmap = (int32_t *)dev_alloc(128 * sizeof(int32_t));
   RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 4 * sizeof(int32_t), hipHostMallocDefault));
@@ -1133,10 +1203,18 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
   hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
                      bw->grid_short + bw->nlong, bw->colsum, active);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
-                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, prm.gmode,
+                     prm.grad_r, bw->cw);
   hipLaunchKernelGGL((k_update<VT, B, GRAD>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, Ucur, Uprev, Y, bw->ctrl, bw->part, bw->ldp, active, (double *)bw->P,
-                     (double *)bw->Xp, prm.reorth, bw->rpart);
+                     (double *)bw->Xp, prm.reorth, bw->rpart, (double *)bw->Xf);
+  if (prm.gmode == GRAD_HARVEST) {
+    // a full block of harvested potentials: its edge pass, then the slots are free
+    hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                       (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xf,
+                       (const double *)bw->cw, bw->gacc, (const int32_t *)(bw->qstate + 4));
+    hipLaunchKernelGGL(k_harvest_reset, dim3(1), dim3(256), 0, st, B, bw->qstate, bw->cw);
+  }
   if (prm.reorth > 0) {
     // column sums of the three coefficient slabs (rpart holds [3][B][ldp])
     hipLaunchKernelGGL(k_col_sum, dim3(3 * B), dim3(COL_THREADS), 0, st, bw->rpart, bw->ldp,
@@ -1265,11 +1343,12 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   // fill the slots: control with every column idle pops the first B pairs,
   // then the update writes their start vectors (and zeros elsewhere)
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
-                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, (int32_t)GRAD);
+                     (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, prm.gmode,
+                     prm.grad_r, bw->cw);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
                      bw->part, bw->ldp, bw->qstate + 1, (double *)nullptr, (double *)nullptr, 0,
-                     (double *)nullptr);
+                     (double *)nullptr, (double *)nullptr);
   launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
   RD_HIP(hipGetLastError());
   // every column starts from the sparse q_1, so the first product reads no
@@ -1297,11 +1376,15 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
 
-// Edge gradient of sum_p grad_r[p] r(s_p, t_p): pairs in groups of B (one
-// run per group, no refill), potentials accumulated during the run, then one
-// edge pass per group into an FP64 accumulator.
-// grad_w == nullptr: refinement mode - instead of the edge gradient, each
-// group's results get r = J(phi), the FP64 energy of its potentials.
+// Edge gradient of sum_p grad_r[p] r(s_p, t_p) (grad_w != nullptr): one run
+// over all pairs with refill. Potentials are accumulated during each pair's
+// run; a finished potential is copied to a slot of the harvest block Xf and
+// the column is refilled; every full block of B harvested potentials gets one
+// edge pass into the FP64 accumulator, and the last, partly filled block one
+// more at the end.
+// grad_w == nullptr: refinement mode - pairs in groups of B (one run per
+// group, no refill), then each group's results get r = J(phi), the FP64
+// energy of its potentials.
 template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
@@ -1312,55 +1395,40 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
   if (need > bw->pot_bytes) {
     dev_free(bw->P);
     dev_free(bw->Xp);
-    bw->P = bw->Xp = nullptr;
+    dev_free(bw->Xf);
+    bw->P = bw->Xp = bw->Xf = nullptr;
     bw->pot_bytes = 0;
     bw->P = dev_alloc(need);
     bw->Xp = dev_alloc(need);
     bw->pot_bytes = need;
   }
+  if (!refine && !bw->Xf) bw->Xf = dev_alloc(bw->pot_bytes);
   if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
-  if (!refine) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
   edge_chunks(g, st);
-  for (int32_t off = 0; off < npairs; off += B) {
-    const int32_t nb = std::min<int32_t>(B, npairs - off);
+  if (!refine) {
+    RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
+    RD_HIP(hipMemsetAsync(bw->Xf, 0, need, st));
+    RD_HIP(hipMemsetAsync(bw->cw, 0, 256 * sizeof(double), st));
     RunParams prm = prm0;
-    prm.npairs = nb;
-    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
-    if (refine) {
-      if (g->unit)
-        hipLaunchKernelGGL((k_energy<B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->nch, (const int4 *)g->echunk, g->col, (const double *)nullptr,
-                           (const double *)bw->Xp, bw->part, bw->ldp);
-      else
-        hipLaunchKernelGGL((k_energy<B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                           g->nch, (const int4 *)g->echunk, g->col, (const double *)g->w64,
-                           (const double *)bw->Xp, bw->part, bw->ldp);
-      hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
-                         bw->cw, bw->qstate + 3);
-      hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
-                         (const double *)bw->Xp, (const double *)bw->cw, out + off);
-    } else {
-      hipLaunchKernelGGL(k_grad_weights, dim3(1), dim3(256), 0, st, B, (const LzState *)bw->st,
-                         grad_r ? grad_r + off : nullptr, bw->cw);
-      std::pair<hipEvent_t, hipEvent_t> ev{};
-      if (prof) {
-        // chunks, column and edge ids of the upper entries, the accumulator
-        // read and written, the potential block read once
-        ev = g->timer[2].next(16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
-                              8.0 * B * (double)g->n + 8.0 * B);
-        RD_HIP(hipEventRecord(ev.first, st));
-      }
-      hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                         (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xp,
-                         (const double *)bw->cw, bw->gacc);
-      if (prof) RD_HIP(hipEventRecord(ev.second, st));
+    prm.gmode = GRAD_HARVEST;
+    prm.grad_r = grad_r;
+    if (npairs > 0) batch_run_t<VT, B, true>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    // the last, partly filled harvest block (unused slots have weight zero)
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (prof) {
+      // chunks, column and edge ids of the upper entries, the accumulator
+      // read and written, the potential block read once
+      ev = g->timer[2].next(16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
+                            8.0 * B * (double)g->n + 8.0 * B);
+      RD_HIP(hipEventRecord(ev.first, st));
     }
-    RD_HIP(hipGetLastError());
-  }
-  if (!refine) {
+    hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                       (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xf,
+                       (const double *)bw->cw, bw->gacc, (const int32_t *)nullptr);
+    if (prof) RD_HIP(hipEventRecord(ev.second, st));
     hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
                        (const double *)bw->gacc, grad_w);
     RD_HIP(hipGetLastError());
@@ -1368,6 +1436,29 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
       RD_HIP(hipStreamSynchronize(st));
       g->timer[2].resolve(g->timer[2].used);
     }
+    return;
+  }
+  for (int32_t off = 0; off < npairs; off += B) {
+    const int32_t nb = std::min<int32_t>(B, npairs - off);
+    RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
+    RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
+    RunParams prm = prm0;
+    prm.npairs = nb;
+    prm.gmode = GRAD_GROUPS;
+    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
+    if (g->unit)
+      hipLaunchKernelGGL((k_energy<B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                         g->nch, (const int4 *)g->echunk, g->col, (const double *)nullptr,
+                         (const double *)bw->Xp, bw->part, bw->ldp);
+    else
+      hipLaunchKernelGGL((k_energy<B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+                         g->nch, (const int4 *)g->echunk, g->col, (const double *)g->w64,
+                         (const double *)bw->Xp, bw->part, bw->ldp);
+    hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
+                       bw->cw, bw->qstate + 3);
+    hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
+                       (const double *)bw->Xp, (const double *)bw->cw, out + off);
+    RD_HIP(hipGetLastError());
   }
 }
 
@@ -1393,7 +1484,7 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
                      bw->part, bw->ldp, bw->qstate + 3, (double *)nullptr, (double *)nullptr, 0,
-                     (double *)nullptr);
+                     (double *)nullptr, (double *)nullptr);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
