@@ -210,7 +210,7 @@ def run_other(name, args):
                      speedup_batched_fp64_vs_plain_fp64=round(b64q / plain_qps, 2),
                      batched_fp32_refined={"value": round(bq, 3), "unit": "queries/s", "eps_rel": 1e-5,
                                            "max_rel_err": float(np.max(np.abs(bout['r'][:8] - ref) / ref)),
-                                           "roofline": dict(broof, note="refinement adds two FP64 vector streams"),
+                                           "roofline": dict(broof, note="refinement adds the two potential streams (P, X)"),
                                            "speedup_vs_plain_fp64": round(bq / plain_qps, 2)},
                      roofline=b64roof,
                      cpu_baseline={"value": round(1.0 / (per_it * float(pit.mean())), 6), "unit": "queries/s",
@@ -238,7 +238,7 @@ def run_other(name, args):
         dt = time.time() - t0
         gms, gl, gbytes = G.kernel_stats(2)
         gavg = gms / max(gl, 1)
-        groof = {"kernel": "k_grad_edges (edge pass, FP64 potentials of 64 pairs)", "bound": "hbm",
+        groof = {"kernel": "k_grad_edges (edge pass over 64 harvested potentials, FP32)", "bound": "hbm",
                  "achieved": round(gbytes / (gavg * 1e-3) / 1e9, 1) if gl else None, "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": round(gbytes / (gavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if gl else None,
                  "traffic": None, "avg_launch_ms": round(gavg, 4), "launches": gl, "alg_bytes_per_launch": gbytes}

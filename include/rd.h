@@ -219,7 +219,7 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
  * gathered vector block read once, the previous block read and the result
  * block written, and the degree arrays. Edge pass: its work items, the column
  * and edge id of every edge, the FP64 accumulator read and written, and the
- * FP64 potential block read once.
+ * potential block (stored in the run's vector precision) read once.
  */
 rd_status rd_kernel_stats(rd_graph g, int32_t which, double *total_ms, int64_t *launches,
                           double *alg_bytes);

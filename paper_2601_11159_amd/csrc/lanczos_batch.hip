@@ -45,14 +45,22 @@ constexpr int COL_THREADS = 256;
 // copied into slot hslot of the block of finished potentials (COL_FINAL with
 // hslot >= 0, or COL_HARVEST for a potential already complete); COL_PENDING
 // waits for a free slot. The slot is refilled after its potential is copied.
+// COL_FINAL_REFILL / COL_HARVEST_REFILL: the same, and in the same update the
+// column starts the next pair (its potential columns are zeroed after the copy).
 enum : int32_t {
   COL_RUN = 0,
   COL_REFILL = 1,
   COL_IDLE = 2,
   COL_FINAL = 3,
   COL_HARVEST = 4,
-  COL_PENDING = 5
+  COL_PENDING = 5,
+  COL_FINAL_REFILL = 6,
+  COL_HARVEST_REFILL = 7
 };
+
+__device__ __forceinline__ bool starts_pair(int32_t mode) {
+  return mode == COL_REFILL || mode == COL_FINAL_REFILL || mode == COL_HARVEST_REFILL;
+}
 
 // gradient handling of a batched run
 enum : int32_t { GRAD_NONE = 0, GRAD_GROUPS = 1, GRAD_HARVEST = 2 };
@@ -87,6 +95,22 @@ __device__ __forceinline__ VecN<VT, N> vload(const VT *p) {
 template <typename VT, int N>
 __device__ __forceinline__ void vstore(VT *p, const VecN<VT, N> &x) {
   *reinterpret_cast<VecN<VT, N> *>(p) = x;
+}
+// loads of stored values widened to FP64, stores of FP64 values rounded once
+template <typename T, int N>
+__device__ __forceinline__ VecN<double, N> vload_f64(const T *p) {
+  const VecN<T, N> x = vload<T, N>(p);
+  VecN<double, N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.v[i] = (double)x.v[i];
+  return r;
+}
+template <typename T, int N>
+__device__ __forceinline__ void vstore_from_f64(T *p, const VecN<double, N> &x) {
+  VecN<T, N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.v[i] = (T)x.v[i];
+  vstore<T, N>(p, r);
 }
 
 template <int B>
@@ -417,7 +441,8 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       slot[c] = -1;
       if (wants[c] && used < B) slot[c] = used++;
       newpair[c] = -2;
-      if (!need[c]) continue;
+      // a finished column whose potential gets a slot now starts the next pair at once
+      if (!need[c] && !(wants[c] && slot[c] >= 0)) continue;
       int32_t idx = -1;
       while (head < prm.npairs) {
         const int32_t cand = head++;
@@ -440,18 +465,33 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
     const int32_t np = newpair[j];
     if (harvest && (fin || pending)) {
       // finished: last potential term (if this iteration added one), then the
-      // copy to a harvest slot, or wait for one
+      // copy to a harvest slot, or wait for one; with a slot and a pair left,
+      // the next pair starts in the same update (cc.sig keeps the finished
+      // run's scale for its last term; k_first_batch sets the new one)
       const bool final_term = fin && advanced && S.status != LZ_BREAKDOWN;
       const int32_t sl = slot[j];
       if (sl >= 0) cw[sl] = (grad_r ? grad_r[S.pair] : 1.0) * S.c;
-      S.status = LZ_IDLE;
-      cc.mode = final_term ? COL_FINAL : (sl >= 0 ? COL_HARVEST : COL_PENDING);
       cc.hslot = sl;
       cc.pa = pa;
       cc.xb = xb;
       cc.pc = 0.0;
       cc.coef = 0.0;
       cc.upd_sparse = 0;
+      if (sl >= 0 && np >= 0) {
+        const int32_t s = ps[np], t = pt[np];
+        const double c = 1.0 / deg[s] + 1.0 / deg[t];
+        state_start(S, s, t, c, prm.tol, prm.max_iters, prm.fixed_k, prm.delay, prm.err_mode, np);
+        const double rc = 1.0 / sqrt(c);
+        cc.mode = final_term ? COL_FINAL_REFILL : COL_HARVEST_REFILL;
+        cc.vs = rc / deg[s];
+        cc.vt = -rc / deg[t];
+        cc.prev_sparse = 0;
+        cc.s = s;
+        cc.t = t;
+      } else {
+        S.status = LZ_IDLE;
+        cc.mode = final_term ? COL_FINAL : (sl >= 0 ? COL_HARVEST : COL_PENDING);
+      }
       active = 1;
     } else if (np >= 0) {
       const int32_t s = ps[np], t = pt[np];
@@ -523,9 +563,9 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
                                                           const ColCtrl *__restrict__ ctrl,
                                                           double *__restrict__ part, int32_t ldp,
                                                           const int32_t *__restrict__ active,
-                                                          double *__restrict__ P, double *__restrict__ X,
+                                                          VT *__restrict__ P, VT *__restrict__ X,
                                                           int32_t ro, double *__restrict__ rpart,
-                                                          double *__restrict__ Xf) {
+                                                          VT *__restrict__ Xf) {
   if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -554,8 +594,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     psp[v] = cc.upd_sparse != 0;
     hs[v] = cc.hslot;
     acc[v] = a1[v] = ac[v] = ap[v] = 0.0;
-    pot = pot || mode[v] == COL_RUN || mode[v] == COL_FINAL || mode[v] == COL_HARVEST ||
-          mode[v] == COL_REFILL;
+    pot = pot || (mode[v] != COL_IDLE && mode[v] != COL_PENDING);
   }
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
@@ -589,26 +628,27 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_update(int32_t n, const doubl
     vstore<VT, VEC>(Y + (size_t)r * B + c0, o);
     if constexpr (GRAD) {
       if (pot) {
-        VecN<double, VEC> pv = vload<double, VEC>(P + (size_t)r * B + c0);
-        VecN<double, VEC> xv = vload<double, VEC>(X + (size_t)r * B + c0);
+        VecN<double, VEC> pv = vload_f64<VT, VEC>(P + (size_t)r * B + c0);
+        VecN<double, VEC> xv = vload_f64<VT, VEC>(X + (size_t)r * B + c0);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-          if (mode[v] == COL_RUN || mode[v] == COL_FINAL) {
+          const int32_t m = mode[v];
+          if (m == COL_RUN || m == COL_FINAL || m == COL_FINAL_REFILL) {
             const double p = (double)sig[v] * (double)uc.v[v] + pa[v] * pv.v[v];
             pv.v[v] = p;
             xv.v[v] += xb[v] * p;
-          } else if (mode[v] == COL_REFILL) {
+          }
+          // a finished potential goes to its harvest slot
+          if ((m == COL_FINAL || m == COL_HARVEST || m == COL_FINAL_REFILL || m == COL_HARVEST_REFILL) &&
+              hs[v] >= 0)
+            Xf[(size_t)r * B + hs[v]] = (VT)xv.v[v];
+          if (starts_pair(m)) {
             pv.v[v] = 0.0;  // a new run's potential starts from zero
             xv.v[v] = 0.0;
           }
         }
-        vstore<double, VEC>(P + (size_t)r * B + c0, pv);
-        vstore<double, VEC>(X + (size_t)r * B + c0, xv);
-        // a finished potential goes to its harvest slot
-#pragma unroll
-        for (int v = 0; v < VEC; ++v)
-          if ((mode[v] == COL_FINAL || mode[v] == COL_HARVEST) && hs[v] >= 0)
-            Xf[(size_t)r * B + hs[v]] = xv.v[v];
+        vstore_from_f64<VT, VEC>(P + (size_t)r * B + c0, pv);
+        vstore_from_f64<VT, VEC>(X + (size_t)r * B + c0, xv);
       }
     }
   }
@@ -715,10 +755,10 @@ __device__ __forceinline__ double segment_sum(double x) {
 // One row segment (LPR lanes over the columns) per edge chunk; four edges in
 // flight per segment; FP64 sums in a fixed order.
 // gate != nullptr: run only when *gate == B (a full block of harvested potentials).
-template <int B>
+template <typename PT, int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
     int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const double *__restrict__ X, const double *__restrict__ cw,
+    const int32_t *__restrict__ eid, const PT *__restrict__ X, const double *__restrict__ cw,
     double *__restrict__ gacc, const int32_t *__restrict__ gate) {
   if (gate && *gate != B) return;
   using S = Shape<B>;
@@ -734,12 +774,12 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
   for (int32_t ic = gw * S::RPW + sub; ic < nch; ic += nwv * S::RPW) {
     const int4 ch = chunk[ic];
     const int32_t u = ch.x, pe = ch.z;
-    const XV xu = vload<double, VEC>(X + (size_t)u * B + c0);
+    const XV xu = vload_f64<PT, VEC>(X + (size_t)u * B + c0);
     int32_t p = ch.y;
     for (; p + 4 <= pe; p += 4) {
       XV xv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) xv[k] = vload<double, VEC>(X + (size_t)col[p + k] * B + c0);
+      for (int k = 0; k < 4; ++k) xv[k] = vload_f64<PT, VEC>(X + (size_t)col[p + k] * B + c0);
       double sk[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -757,7 +797,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
       }
     }
     for (; p < pe; ++p) {
-      const XV xv = vload<double, VEC>(X + (size_t)col[p] * B + c0);
+      const XV xv = vload_f64<PT, VEC>(X + (size_t)col[p] * B + c0);
       double a = 0.0;
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
@@ -783,10 +823,10 @@ __global__ void k_harvest_reset(int32_t B, int32_t *__restrict__ qstate, double 
 
 // Per-column energy of the accumulated potentials, sum_e w_e (X[u,p] - X[v,p])^2
 // in FP64, as per-block column partials (edge chunks as in k_grad_edges).
-template <int B, bool WEIGHTED>
+template <typename PT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
     int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
-    const double *__restrict__ w64, const double *__restrict__ X, double *__restrict__ part,
+    const double *__restrict__ w64, const PT *__restrict__ X, double *__restrict__ part,
     int32_t ldp) {
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
@@ -802,12 +842,12 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
   for (int32_t ic = gw * S::RPW + sub; ic < nch; ic += nwv * S::RPW) {
     const int4 ch = chunk[ic];
     const int32_t u = ch.x, pe = ch.z;
-    const XV xu = vload<double, VEC>(X + (size_t)u * B + c0);
+    const XV xu = vload_f64<PT, VEC>(X + (size_t)u * B + c0);
     int32_t p = ch.y;
     for (; p + 4 <= pe; p += 4) {
       XV xv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) xv[k] = vload<double, VEC>(X + (size_t)col[p + k] * B + c0);
+      for (int k = 0; k < 4; ++k) xv[k] = vload_f64<PT, VEC>(X + (size_t)col[p + k] * B + c0);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double we = WEIGHTED ? w64[p + k] : 1.0;
@@ -819,7 +859,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
       }
     }
     for (; p < pe; ++p) {
-      const XV xv = vload<double, VEC>(X + (size_t)col[p] * B + c0);
+      const XV xv = vload_f64<PT, VEC>(X + (size_t)col[p] * B + c0);
       const double we = WEIGHTED ? w64[p] : 1.0;
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
@@ -833,13 +873,13 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
 
 // r = J(phi) = 2 (phi_s - phi_t) - phi^T L phi with phi = sqrt(c) X[:, j] (FP64).
 template <typename VT, int B>
-__global__ void k_refine_out(const LzState *__restrict__ st, const double *__restrict__ X,
+__global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restrict__ X,
                              const double *__restrict__ energy, rd_result *__restrict__ out) {
   const int j = threadIdx.x;
   if (j >= B) return;
   const LzState &S = st[j];
   if (S.pair < 0) return;
-  const double xs = X[(size_t)S.s * B + j], xt = X[(size_t)S.t * B + j];
+  const double xs = (double)X[(size_t)S.s * B + j], xt = (double)X[(size_t)S.t * B + j];
   out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
 }
 
@@ -881,11 +921,11 @@ template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(256) void k_first_batch(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ w64, const double *__restrict__ deg, VT *__restrict__ W,
-    LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, double *__restrict__ P, double *__restrict__ X,
+    LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, VT *__restrict__ P, VT *__restrict__ X,
     const int32_t *__restrict__ active) {
   if (*active == 0) return;
   const int j = blockIdx.x;
-  if (ctrl[j].mode != COL_REFILL) return;
+  if (!starts_pair(ctrl[j].mode)) return;
   __shared__ double sm[256 / 64 + 2];
   __shared__ LzState S0;
   if (threadIdx.x == 0) S0 = st[j];
@@ -909,10 +949,10 @@ __global__ __launch_bounds__(256) void k_first_batch(
     if (GRAD && advanced) {
       const double rc = 1.0 / sqrt(S.c);
       const double q1s = rc / deg[s], q1t = -rc / deg[t];
-      P[(size_t)s * B + j] = q1s;
-      P[(size_t)t * B + j] = q1t;
-      X[(size_t)s * B + j] = q1s / S.delta;
-      X[(size_t)t * B + j] = q1t / S.delta;
+      P[(size_t)s * B + j] = (VT)q1s;
+      P[(size_t)t * B + j] = (VT)q1t;
+      X[(size_t)s * B + j] = (VT)(q1s / S.delta);
+      X[(size_t)t * B + j] = (VT)(q1t / S.delta);
     }
     cc.mode = COL_RUN;
     cc.coef = 0.0;
@@ -1002,7 +1042,7 @@ struct BatchWork {
   double *rsum = nullptr;    // [3 * 256]
   // gradient mode: search directions and potentials (n x B each), edge accumulator
   void *P = nullptr, *Xp = nullptr;
-  void *Xf = nullptr;  // gradient harvest mode: n x B finished potentials (FP64)
+  void *Xf = nullptr;  // gradient harvest mode: n x B finished potentials
   size_t pot_bytes = 0;
   double *gacc = nullptr;  // [m]
   double *cw = nullptr;    // [256]
@@ -1172,7 +1212,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Upr
 template <typename VT, int B, bool GRAD>
 static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
   hipLaunchKernelGGL((k_first_batch<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->row_ptr, g->col,
-                     (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (double *)bw->P, (double *)bw->Xp,
+                     (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (VT *)bw->P, (VT *)bw->Xp,
                      bw->qstate + 1);
 }
 
@@ -1206,12 +1246,12 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, prm.gmode,
                      prm.grad_r, bw->cw);
   hipLaunchKernelGGL((k_update<VT, B, GRAD>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     g->deg, Ucur, Uprev, Y, bw->ctrl, bw->part, bw->ldp, active, (double *)bw->P,
-                     (double *)bw->Xp, prm.reorth, bw->rpart, (double *)bw->Xf);
+                     g->deg, Ucur, Uprev, Y, bw->ctrl, bw->part, bw->ldp, active, (VT *)bw->P,
+                     (VT *)bw->Xp, prm.reorth, bw->rpart, (VT *)bw->Xf);
   if (prm.gmode == GRAD_HARVEST) {
     // a full block of harvested potentials: its edge pass, then the slots are free
-    hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                       (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xf,
+    hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                       (const int4 *)g->echunk, g->col, g->eid, (const VT *)bw->Xf,
                        (const double *)bw->cw, bw->gacc, (const int32_t *)(bw->qstate + 4));
     hipLaunchKernelGGL(k_harvest_reset, dim3(1), dim3(256), 0, st, B, bw->qstate, bw->cw);
   }
@@ -1347,8 +1387,8 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
                      prm.grad_r, bw->cw);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
-                     bw->part, bw->ldp, bw->qstate + 1, (double *)nullptr, (double *)nullptr, 0,
-                     (double *)nullptr, (double *)nullptr);
+                     bw->part, bw->ldp, bw->qstate + 1, (VT *)nullptr, (VT *)nullptr, 0,
+                     (double *)nullptr, (VT *)nullptr);
   launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
   RD_HIP(hipGetLastError());
   // every column starts from the sparse q_1, so the first product reads no
@@ -1391,7 +1431,7 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
                        rd_result *out, float *grad_w, hipStream_t st, bool prof) {
   const bool refine = grad_w == nullptr;
   batch_reserve(g, bw, B, sizeof(VT));
-  const size_t need = (size_t)g->n * B * sizeof(double);  // potentials kept in FP64
+  const size_t need = (size_t)g->n * B * sizeof(VT);  // potentials stored like the vectors
   if (need > bw->pot_bytes) {
     dev_free(bw->P);
     dev_free(bw->Xp);
@@ -1422,11 +1462,11 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
       // chunks, column and edge ids of the upper entries, the accumulator
       // read and written, the potential block read once
       ev = g->timer[2].next(16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
-                            8.0 * B * (double)g->n + 8.0 * B);
+                            (double)sizeof(VT) * B * (double)g->n + 8.0 * B);
       RD_HIP(hipEventRecord(ev.first, st));
     }
-    hipLaunchKernelGGL((k_grad_edges<B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                       (const int4 *)g->echunk, g->col, g->eid, (const double *)bw->Xf,
+    hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                       (const int4 *)g->echunk, g->col, g->eid, (const VT *)bw->Xf,
                        (const double *)bw->cw, bw->gacc, (const int32_t *)nullptr);
     if (prof) RD_HIP(hipEventRecord(ev.second, st));
     hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
@@ -1447,17 +1487,17 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     prm.gmode = GRAD_GROUPS;
     batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
     if (g->unit)
-      hipLaunchKernelGGL((k_energy<B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+      hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
                          g->nch, (const int4 *)g->echunk, g->col, (const double *)nullptr,
-                         (const double *)bw->Xp, bw->part, bw->ldp);
+                         (const VT *)bw->Xp, bw->part, bw->ldp);
     else
-      hipLaunchKernelGGL((k_energy<B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
+      hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
                          g->nch, (const int4 *)g->echunk, g->col, (const double *)g->w64,
-                         (const double *)bw->Xp, bw->part, bw->ldp);
+                         (const VT *)bw->Xp, bw->part, bw->ldp);
     hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                        bw->cw, bw->qstate + 3);
     hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
-                       (const double *)bw->Xp, (const double *)bw->cw, out + off);
+                       (const VT *)bw->Xp, (const double *)bw->cw, out + off);
     RD_HIP(hipGetLastError());
   }
 }
@@ -1483,8 +1523,8 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
-                     bw->part, bw->ldp, bw->qstate + 3, (double *)nullptr, (double *)nullptr, 0,
-                     (double *)nullptr, (double *)nullptr);
+                     bw->part, bw->ldp, bw->qstate + 3, (VT *)nullptr, (VT *)nullptr, 0,
+                     (double *)nullptr, (VT *)nullptr);
   hipEvent_t e0, e1;
   RD_HIP(hipEventCreate(&e0));
   RD_HIP(hipEventCreate(&e1));
