@@ -15,10 +15,14 @@
 namespace {
 
 constexpr int SMALL_THREADS = 512;
+constexpr int HOIST_ROWS = 8;  // rows per thread whose degrees stay in registers (n <= 4096)
 
-template <typename VT, bool WEIGHTED>
+// CSR_LDS: the row offsets, column ids (and weights) are copied to LDS once,
+// after the two vectors, so an iteration touches no global memory.
+// HOIST: each thread's (at most HOIST_ROWS) rows keep d_u and 1/d_u in registers.
+template <typename VT, bool WEIGHTED, bool CSR_LDS, bool HOIST>
 __global__ __launch_bounds__(SMALL_THREADS) void k_small(
-    int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const VT *__restrict__ w, const VT *__restrict__ invdeg, const double *__restrict__ deg,
     int32_t npairs, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt, int32_t s0,
     int32_t t0, double tol,
@@ -36,6 +40,38 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small(
     if (threadIdx.x == 0) out[pair] = rd_result{0.0, 0.0, 0, RD_OK};
     return;
   }
+  const int32_t *RP = row_ptr;
+  const int32_t *CL = col;
+  const VT *WL = w;
+  if constexpr (CSR_LDS) {
+    int32_t *rp_l = reinterpret_cast<int32_t *>(bufB + n);
+    int32_t *col_l = rp_l + (n + 1);
+    for (int32_t i = threadIdx.x; i <= n; i += SMALL_THREADS) rp_l[i] = row_ptr[i];
+    for (int32_t i = threadIdx.x; i < nnz; i += SMALL_THREADS) col_l[i] = col[i];
+    if constexpr (WEIGHTED) {
+      // weights after the column ids, aligned to their size
+      const size_t off = ((size_t)(n + 1 + nnz) * 4 + sizeof(VT) - 1) / sizeof(VT) * sizeof(VT);
+      VT *w_l = reinterpret_cast<VT *>(reinterpret_cast<unsigned char *>(rp_l) + off);
+      for (int32_t i = threadIdx.x; i < nnz; i += SMALL_THREADS) w_l[i] = w[i];
+      WL = w_l;
+    }
+    RP = rp_l;
+    CL = col_l;
+  }
+  double dg[HOIST ? HOIST_ROWS : 1];
+  VT idg[HOIST ? HOIST_ROWS : 1];
+  int32_t rb[HOIST ? HOIST_ROWS : 1], re[HOIST ? HOIST_ROWS : 1];
+  if constexpr (HOIST) {
+    if constexpr (CSR_LDS) __syncthreads();  // the row offsets in LDS are complete
+#pragma unroll
+    for (int k = 0; k < HOIST_ROWS; ++k) {
+      const int32_t r = threadIdx.x + k * SMALL_THREADS;
+      dg[k] = r < n ? deg[r] : 0.0;
+      idg[k] = r < n ? invdeg[r] : VT(0);
+      rb[k] = r < n ? RP[r] : 0;
+      re[k] = r < n ? RP[r + 1] : 0;
+    }
+  }
   const double c = 1.0 / deg[s] + 1.0 / deg[t];
   const double rc = 1.0 / sqrt(c);
   for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) {
@@ -47,21 +83,60 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small(
   if (threadIdx.x == 0) state_start(S, s, t, c, tol, max_iters, fixed_k, delay, err_mode, pair);
   __syncthreads();
   VT *Ucur = bufA, *Uprev = bufB;
+  // one row of y = sig D^{-1} W U_cur - pc U_prev (over U_prev); returns its
+  // contribution to <y, q>_D
+  auto spmv_row = [&](int32_t r, VT sig, VT pc, bool has_prev, double d, VT id) {
+    VT acc = 0;
+    const int32_t pe = RP[r + 1];
+    for (int32_t p = RP[r]; p < pe; ++p) {
+      const VT x = Ucur[CL[p]];
+      acc += WEIGHTED ? WL[p] * x : x;
+    }
+    VT y = sig * acc * id;
+    if (has_prev) y -= pc * Uprev[r];
+    Uprev[r] = y;
+    return d * (double)y * ((double)sig * (double)Ucur[r]);
+  };
   for (;;) {
     const VT sig = (VT)S.sig_cur, pc = (VT)S.prev_coef;
     const bool has_prev = S.prev_coef != 0.0;
-    // y = sig D^{-1} W U_cur - pc U_prev, over U_prev; <y, q>_D
     double apart = 0.0;
-    for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) {
-      VT acc = 0;
-      for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
-        const VT x = Ucur[col[p]];
-        acc += WEIGHTED ? w[p] * x : x;
+    if constexpr (HOIST) {
+      // the first FRONT entries of all of this thread's rows in flight
+      // together: every column id, then every gather
+      constexpr int FRONT = 4;
+      int32_t ci[HOIST_ROWS][FRONT];
+#pragma unroll
+      for (int k = 0; k < HOIST_ROWS; ++k)
+#pragma unroll
+        for (int e = 0; e < FRONT; ++e) ci[k][e] = rb[k] + e < re[k] ? CL[rb[k] + e] : -1;
+      VT acc[HOIST_ROWS];
+#pragma unroll
+      for (int k = 0; k < HOIST_ROWS; ++k) {
+        VT x[FRONT];
+#pragma unroll
+        for (int e = 0; e < FRONT; ++e) x[e] = ci[k][e] >= 0 ? Ucur[ci[k][e]] : VT(0);
+        VT a = 0;
+#pragma unroll
+        for (int e = 0; e < FRONT; ++e) a += WEIGHTED && ci[k][e] >= 0 ? WL[rb[k] + e] * x[e] : x[e];
+        acc[k] = a;
       }
-      VT y = sig * acc * invdeg[r];
-      if (has_prev) y -= pc * Uprev[r];
-      Uprev[r] = y;
-      apart += deg[r] * (double)y * ((double)sig * (double)Ucur[r]);
+#pragma unroll
+      for (int k = 0; k < HOIST_ROWS; ++k) {
+        const int32_t r = threadIdx.x + k * SMALL_THREADS;
+        if (r >= n) continue;
+        for (int32_t p = rb[k] + FRONT; p < re[k]; ++p) {
+          const VT x = Ucur[CL[p]];
+          acc[k] += WEIGHTED ? WL[p] * x : x;
+        }
+        VT y = sig * acc[k] * idg[k];
+        if (has_prev) y -= pc * Uprev[r];
+        Uprev[r] = y;
+        apart += dg[k] * (double)y * ((double)sig * (double)Ucur[r]);
+      }
+    } else {
+      for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS)
+        apart += spmv_row(r, sig, pc, has_prev, deg[r], invdeg[r]);
     }
     const double alpha = block_sum(apart, red);
     if (threadIdx.x == 0) scalar_after_alpha(S, alpha, tr_alpha, tr_rhat);
@@ -70,10 +145,22 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small(
     // w = y - alpha q_i; ||w||_D^2
     const VT coef = (VT)(S.alpha * S.sig_cur);
     double bacc = 0.0;
-    for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) {
-      const VT x = Uprev[r] - coef * Ucur[r];
-      Uprev[r] = x;
-      bacc += deg[r] * ((double)x * (double)x);
+    if constexpr (HOIST) {
+#pragma unroll
+      for (int k = 0; k < HOIST_ROWS; ++k) {
+        const int32_t r = threadIdx.x + k * SMALL_THREADS;
+        if (r < n) {
+          const VT x = Uprev[r] - coef * Ucur[r];
+          Uprev[r] = x;
+          bacc += dg[k] * ((double)x * (double)x);
+        }
+      }
+    } else {
+      for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) {
+        const VT x = Uprev[r] - coef * Ucur[r];
+        Uprev[r] = x;
+        bacc += deg[r] * ((double)x * (double)x);
+      }
     }
     const double bb = block_sum(bacc, red);
     if (threadIdx.x == 0) scalar_after_beta(S, bb, tr_beta);
@@ -108,37 +195,55 @@ bool small_eligible(rd_graph g, const rd_options &o) {
   return 2 * (size_t)g->n * vt <= small_lds_limit(g);
 }
 
+// LDS bytes of the two vectors and, when csr, of the row offsets, column ids
+// and weights after them.
+static size_t small_lds_bytes(rd_graph g, size_t vt, bool csr) {
+  size_t b = 2 * (size_t)g->n * vt;
+  if (csr) {
+    b += ((size_t)(g->n + 1) + (size_t)g->nnz) * 4;
+    if (!g->unit) b = (b + vt - 1) / vt * vt + (size_t)g->nnz * vt;
+  }
+  return b;
+}
+
+template <typename VT, bool WEIGHTED>
+static void small_launch(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t s0,
+                         int32_t t0, double eps, const rd_options &o, hipStream_t st, rd_result *out,
+                         double *tr_alpha, double *tr_beta, double *tr_rhat) {
+  const bool csr = small_lds_bytes(g, sizeof(VT), true) <= small_lds_limit(g);
+  const bool hoist = g->n <= SMALL_THREADS * HOIST_ROWS;
+  const size_t lds = small_lds_bytes(g, sizeof(VT), csr);
+  const VT *w = (const VT *)(sizeof(VT) == 8 ? (const void *)g->w64 : (const void *)g->w32);
+  const VT *id = (const VT *)(sizeof(VT) == 8 ? (const void *)g->invdeg : (const void *)g->invdeg32);
+  const dim3 grid(npairs), block(SMALL_THREADS);
+#define RD_SMALL_LAUNCH(CSR, HOIST)                                                                  \
+  hipLaunchKernelGGL((k_small<VT, WEIGHTED, CSR, HOIST>), grid, block, lds, st, g->n, (int32_t)g->nnz, \
+                     g->row_ptr, g->col, WEIGHTED ? w : (const VT *)nullptr, id, g->deg, npairs, ps,  \
+                     pt, s0, t0, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, out, tr_alpha,     \
+                     tr_beta, tr_rhat)
+  if (csr && hoist) RD_SMALL_LAUNCH(true, true);
+  else if (csr) RD_SMALL_LAUNCH(true, false);
+  else if (hoist) RD_SMALL_LAUNCH(false, true);
+  else RD_SMALL_LAUNCH(false, false);
+#undef RD_SMALL_LAUNCH
+}
+
 // npairs pairs (device arrays), one workgroup each; results to device `out`.
 // ps == nullptr: a single pair (s0, t0).
 void small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t s0,
                int32_t t0, double eps, const rd_options &o, hipStream_t st, rd_result *out,
                double *tr_alpha, double *tr_beta, double *tr_rhat) {
   if (npairs <= 0) return;
-  const size_t vt = o.precision == RD_F64 ? sizeof(double) : sizeof(float);
-  const size_t lds = 2 * (size_t)g->n * vt;
-  const dim3 grid(npairs), block(SMALL_THREADS);
   if (o.precision == RD_F64) {
     if (g->unit)
-      hipLaunchKernelGGL((k_small<double, false>), grid, block, lds, st, g->n, g->row_ptr, g->col,
-                         (const double *)nullptr, (const double *)g->invdeg, g->deg, npairs, ps, pt,
-                         s0, t0, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, out, tr_alpha, tr_beta,
-                         tr_rhat);
+      small_launch<double, false>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
     else
-      hipLaunchKernelGGL((k_small<double, true>), grid, block, lds, st, g->n, g->row_ptr, g->col,
-                         (const double *)g->w64, (const double *)g->invdeg, g->deg, npairs, ps, pt,
-                         s0, t0, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, out, tr_alpha, tr_beta,
-                         tr_rhat);
+      small_launch<double, true>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
   } else {
     if (g->unit)
-      hipLaunchKernelGGL((k_small<float, false>), grid, block, lds, st, g->n, g->row_ptr, g->col,
-                         (const float *)nullptr, (const float *)g->invdeg32, g->deg, npairs, ps, pt,
-                         s0, t0, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, out, tr_alpha, tr_beta,
-                         tr_rhat);
+      small_launch<float, false>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
     else
-      hipLaunchKernelGGL((k_small<float, true>), grid, block, lds, st, g->n, g->row_ptr, g->col,
-                         (const float *)g->w32, (const float *)g->invdeg32, g->deg, npairs, ps, pt,
-                         s0, t0, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode, out, tr_alpha, tr_beta,
-                         tr_rhat);
+      small_launch<float, true>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
   }
   RD_HIP(hipGetLastError());
 }

@@ -230,3 +230,26 @@ def test_reorth_long_run_past_convergence_stays_at_the_truth(ro):
     out = G.query(3, 150, 1.0, rd.rd_default_options(fixed_k=600, reorth=ro))
     assert out.iters == 600
     assert out.r == pytest.approx(147.0, rel=1e-8)
+
+
+def test_single_workgroup_variants():
+    # the one-workgroup kernel stages the CSR in LDS when it fits beside the two
+    # vectors and keeps degrees in registers when n <= 4096; each combination
+    # against closed forms or the oracle, plain and batched
+    cases = [
+        (I.grid(64, 64), rd.RD_F64),     # CSR in LDS, degrees in registers
+        (I.random_tree(5000, seed=83), rd.RD_F64),  # CSR in LDS, n > 4096
+        (I.grid(80, 80), rd.RD_F64),     # neither (CSR does not fit)
+        (I.random_tree(3000, seed=81, weighted=True), rd.RD_F64),  # weights in LDS
+    ]
+    for g, prec in cases:
+        G = _graph(g)
+        s, t = I.uniform_pairs(g.n, 6, seed=82)
+        A, d = LZ.normalized_adjacency(g)
+        truth = np.array([LZ.lanczos_rd(g, int(a), int(b), tol=1e-13, A=A, d=d).r for a, b in zip(s, t)])
+        eps, bar = 1e-10, 1e-8
+        o = rd.rd_default_options(precision=prec, max_iters=100000)
+        res = np.array([G.query(int(a), int(b), eps, o).r for a, b in zip(s, t)])
+        assert np.max(np.abs(res - truth) / truth) <= bar, g.name
+        out = G.query_batch(s, t, eps, o)
+        assert np.max(np.abs(out["r"] - truth) / truth) <= bar, g.name
