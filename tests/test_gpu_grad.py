@@ -179,3 +179,23 @@ def test_gradient_and_refinement_on_hub_rows(width):
     out = G.query_batch(s, t, 1e-10, _opts(block_width=width, refine=1))
     assert out["r"][5] == 0.0
     np.testing.assert_allclose(out["r"][mask], truth, rtol=1e-9)
+
+
+def test_gradient_degenerate_inputs():
+    g = I.random_connected(300, extra=900, seed=91, weighted=True)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    # every pair has s == t: r = 0 and a zero gradient
+    s = np.arange(20, dtype=np.int32)
+    fwd, gw = G.grad_edges(s, s.copy(), None, 1e-8, _opts(block_width=16))
+    assert np.all(fwd["r"] == 0.0) and np.all(fwd["iters"] == 0)
+    assert np.all(gw == 0.0)
+    # no pairs at all
+    fwd0, gw0 = G.grad_edges(np.zeros(0, np.int32), np.zeros(0, np.int32), None, 1e-8, _opts(block_width=16))
+    assert len(fwd0) == 0 and np.all(gw0 == 0.0)
+    # the same pair many times: the gradient is the single-pair gradient times the count
+    s1 = np.full(37, 5, np.int32)
+    t1 = np.full(37, 250, np.int32)
+    f1, g1 = G.grad_edges(s1[:1], t1[:1], None, 1e-12, _opts(block_width=16))
+    fn, gn = G.grad_edges(s1, t1, None, 1e-12, _opts(block_width=16))
+    np.testing.assert_allclose(gn, 37 * g1, rtol=1e-5)
+    np.testing.assert_allclose(fn["r"], f1["r"][0], rtol=1e-12)
