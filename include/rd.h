@@ -137,17 +137,26 @@ void rd_default_options(rd_options *o);
 rd_status rd_init_graph(int32_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
                         int32_t w_dtype, uint32_t flags, rd_graph *out);
 
-/* Replace the edge weights (same edge list order, same rules as rd_init_graph). */
+/* Replace the edge weights: w[m] in the edge-list order of rd_init_graph,
+ * finite and > 0 (checked first: RD_E_ARG, and the handle keeps its old
+ * weights). Degrees, their inverses and vol are recomputed;
+ * the structure, and so connectivity, is unchanged. flags: RD_DEVICE_PTRS if w
+ * is a device pointer. */
 rd_status rd_set_weights(rd_graph g, const void *w, int32_t w_dtype, uint32_t flags);
 
 /* n, m and the number of stored adjacency entries (2m). Any pointer may be NULL. */
 rd_status rd_graph_info(rd_graph g, int32_t *n, int64_t *m, int64_t *nnz);
 
 /*
- * One pair, the plain single-pair loop (Algorithm 3). s == t gives r = 0 with
- * iters = 0. eps > 0 is the stopping tolerance (relative unless
- * o->err_mode = 1) unless o->fixed_k > 0. o may be NULL (defaults).
- * out is host memory (RD_DEVICE_PTRS is not accepted here).
+ * One pair, the plain single-pair loop: Algorithm 3 (Section 3) with
+ * r_hat = (1/d_s + 1/d_t) e_1^T (I - T)^{-1} e_1 (Eq. approx_formula).
+ * s == t gives r = 0 with iters = 0. eps > 0 is the stopping tolerance
+ * (relative unless o->err_mode = 1) unless o->fixed_k > 0. o may be NULL
+ * (defaults). out is host memory (RD_DEVICE_PTRS is not accepted here).
+ * Returns RD_E_ARG for s or t outside [0, n) or eps <= 0 without fixed_k;
+ * otherwise RD_OK, with the query's own outcome in out->status (RD_OK,
+ * RD_E_NOT_CONVERGED when max_iters ran out, RD_E_BREAKDOWN) and out->r the
+ * last estimate.
  */
 rd_status rd_query(rd_graph g, int32_t s, int32_t t, double eps, const rd_options *o,
                    rd_result *out);
@@ -162,11 +171,17 @@ rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
                          double *alpha, double *beta, double *rhat, int32_t *iters);
 
 /*
- * Many pairs: npairs independent Lanczos runs advanced together as block
- * columns of one sparse product per iteration; a column that meets eps is
- * retired and its slot refilled with the next pending pair. s, t are int32[npairs]
- * and out rd_result[npairs]; all three are device pointers when o->flags has
- * RD_DEVICE_PTRS.
+ * Many pairs: npairs independent runs of Algorithm 3 advanced together as the
+ * block columns of one sparse product per iteration; a column whose run stops
+ * is retired and its slot refilled with the next pending pair (pairs with
+ * s == t get r = 0 without a slot). s, t are int32[npairs] and out
+ * rd_result[npairs]; all three are device pointers when o->flags has
+ * RD_DEVICE_PTRS. Options: precision, block_width (0: autotuned), reorth,
+ * refine, and the flags RD_NO_COMPACT, RD_GENERAL_PATH, RD_PROFILE. Each
+ * result is that of the same run done alone, up to rounding. Returns RD_E_ARG
+ * for an id outside [0, n) (checked on the device), an unsupported
+ * block_width or eps <= 0 without fixed_k; per-pair outcomes are in
+ * out[p].status as for rd_query.
  */
 rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
                          double eps, const rd_options *o, rd_result *out);
@@ -195,11 +210,16 @@ rd_status rd_batch_schedule(rd_graph g, int32_t *wave_nnz, int32_t *long_deg);
 /*
  * Edge-weight gradient of L = sum_p grad_r[p] r(s_p, t_p):
  *   grad_w[e] = -sum_p grad_r[p] (phi_p(u_e) - phi_p(v_e))^2,
- * with phi_p = L^+ (e_s - e_t) estimated as in line 1 of Algorithm 5 from the
- * same Lanczos run that gives r_hat. grad_r may be NULL (all ones). fwd, when
- * not NULL, receives the forward results (rd_result[npairs]). grad_w is
- * float[m] in edge-list order. When o->flags has RD_DEVICE_PTRS, s, t,
- * grad_r, fwd and grad_w are device pointers.
+ * the derivative of r = b^T L^+ b (b = e_s - e_t, Section 2.1) through
+ * L = sum_e w_e b_e b_e^T, evaluated at the potential phi_p = L^+ b of the
+ * electric-flow definition (Section 6.3), estimated as in line 1 of
+ * Algorithm 5 from the same Lanczos run that gives r_hat (it is the gradient
+ * of the exact r at phi_hat, not of the truncated r_hat_k). grad_r may be
+ * NULL (all ones). fwd, when not NULL, receives the forward results
+ * (rd_result[npairs]). grad_w is float[m] in edge-list order, accumulated in
+ * FP64. When o->flags has RD_DEVICE_PTRS, s, t, grad_r, fwd and grad_w are
+ * device pointers. block_width 0 is autotuned; refine is ignored. Errors as
+ * for rd_query_batch; grad_w == NULL is RD_E_ARG.
  */
 rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
                         const double *grad_r, double eps, const rd_options *o, rd_result *fwd,
@@ -208,10 +228,11 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
 /*
  * Diagnostic: timing of the sparse-product launches recorded by calls made
  * with RD_PROFILE in rd_options.flags, since the previous rd_kernel_stats call
- * (which resets the counters). which = 0: the batched product over rows of
- * length <= 1024 (k_spmm_short); which = 1: the single-pair product (k_spmv);
- * which = 2: the edge pass of rd_grad_edges (k_grad_edges, one launch per
- * group of block_width pairs). Durations come from HIP events recorded around
+ * (which resets the counters). which = 0: the batched product over the rows
+ * up to the long-row threshold (k_spmm_short); which = 1: the single-pair
+ * product (k_spmv); which = 2: the edge pass of rd_grad_edges (k_grad_edges;
+ * the pass over the last block of finished potentials of each call is timed).
+ * Durations come from HIP events recorded around
  * each launch on the stream it runs on. alg_bytes receives the mean
  * algorithmic bytes per counted launch (a batched run that narrows its block
  * counts each launch at its own width). Products: adjacency
