@@ -204,7 +204,9 @@ def run_other(name, args):
                       "path": "batched FP64 at eps 1e-4 (value); plain FP64 at 1e-4 on 8 pairs and "
                               "batched FP32 + FP64 energy refinement at eps 1e-5, width 64, beside it",
                       "block_width": w64, "block_width_source": "autotuned",
-                      "row_schedule": dict(zip(("wave_nnz", "long_deg"), sched))},
+                      "row_schedule": dict(zip(("wave_nnz", "long_deg"), sched)),
+                      "node_order": "as generated (grid order; the degree relabelling breaks the "
+                                    "neighbour locality and is slower here)"},
                      plain_fp64={"value": round(plain_qps, 3), "unit": "queries/s", "mean_iters": float(pit.mean()),
                                  "roofline": proof},
                      speedup_batched_fp64_vs_plain_fp64=round(b64q / plain_qps, 2),
