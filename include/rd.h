@@ -8,7 +8,8 @@
  * D^{-1/2} W D^{-1/2} started from (e_s/sqrt(d_s) - e_t/sqrt(d_t)), whose
  * tridiagonal coefficients give r_hat = (1/d_s + 1/d_t) e_1^T (I - T)^{-1} e_1
  * (Eq. approx_formula). Potentials phi = L^+ (e_s - e_t) and flows follow the
- * electric-flow definition of Section 6.3 and line 1 of Algorithm 5.
+ * electric-flow definition of Section 6.3 and the potential estimate of
+ * Algorithm 5.
  *
  * Conventions shared by every entry point:
  *  - Every call returns rd_status; nothing throws across the ABI. A handle is
@@ -69,6 +70,17 @@ typedef enum {
                                the width (repeatedly, down to 16), so a tail of slow pairs does
                                not pay for idle columns. Results differ only by rounding. */
 
+#define RD_NO_SPARSE2 0x20u /* rd_options.flags: rd_query_batch runs the second Lanczos
+                               iteration of every pair as a dense product over the block.
+                               By default (precision either, reorth 0), a pair whose second
+                               product touches few adjacency entries computes it from the
+                               support of q_2 alone, N(s) u N(t) u {s, t}: each entry
+                               (u, v), u in that support, adds w_uv w_1[u] / d_v to v's
+                               sum in 64-bit fixed point (integer sums do not depend on the
+                               order, so results stay the same from run to run), and the
+                               pair joins the dense iterations at the third. Results differ
+                               only by rounding. Not used by rd_grad_edges or refine. */
+
 /* weight / vector dtypes */
 #define RD_F64 0
 #define RD_F32 1
@@ -90,8 +102,8 @@ typedef struct {
                           and rd_grad_edges are device pointers */
   int32_t refine;      /* rd_query_batch only. 1: report the FP64 energy
                           J = 2 b^T phi - phi^T L phi (b = e_s - e_t) of the
-                          potential phi accumulated by the run (Algorithm 5,
-                          line 1) instead of r_hat. J <= r, and r - J equals
+                          potential phi accumulated by the run (the estimate
+                          of Algorithm 5) instead of r_hat. J <= r, and r - J equals
                           the squared energy-norm error of phi, so rounding in
                           FP32 vectors enters only to second order. Pairs run
                           in groups of block_width without refill. */
@@ -190,14 +202,18 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
  * The block width rd_query_batch uses when rd_options.block_width is 0, and
  * the row-bin schedule of its sparse product. First the width among 32, 64,
  * 128, 256 (not wider than needed for npairs) whose sparse product takes the
- * least time per column on this graph; then, at that width, the schedule
+ * least time per column on this graph (a wider width only when it is at least
+ * 5% faster per column than the narrower best); then, at that width, the schedule
  * (entries per wavefront work item: 128, 256 or 512; rows longer than 512,
  * 1024 or 2048 entries get a workgroup of their own) with the least time.
  * Measured on first use with HIP events on `stream` (NULL: the handle's
  * stream) and kept on the handle per precision; with the environment variable
  * RD_AUTOTUNE_CACHE naming a file, choices are also read from and appended to
- * that file. The chosen schedule stays in effect for later calls, also with
- * an explicit block_width.
+ * that file (one line per graph and precision: key, width, entries per work
+ * item, long-row threshold, product time per column in ms). The chosen
+ * schedule stays in effect for later calls, also with an explicit
+ * block_width. The measured time per column also sets which pairs take the
+ * sparse second iteration (see RD_NO_SPARSE2) when a run uses the tuned width.
  */
 rd_status rd_tune_width(rd_graph g, int32_t precision, int32_t npairs, void *stream, int32_t *width);
 
@@ -212,8 +228,8 @@ rd_status rd_batch_schedule(rd_graph g, int32_t *wave_nnz, int32_t *long_deg);
  *   grad_w[e] = -sum_p grad_r[p] (phi_p(u_e) - phi_p(v_e))^2,
  * the derivative of r = b^T L^+ b (b = e_s - e_t, Section 2.1) through
  * L = sum_e w_e b_e b_e^T, evaluated at the potential phi_p = L^+ b of the
- * electric-flow definition (Section 6.3), estimated as in line 1 of
- * Algorithm 5 from the same Lanczos run that gives r_hat (it is the gradient
+ * electric-flow definition (Section 6.3), estimated as in Algorithm 5 from
+ * the same Lanczos run that gives r_hat (it is the gradient
  * of the exact r at phi_hat, not of the truncated r_hat_k). grad_r may be
  * NULL (all ones). fwd, when not NULL, receives the forward results
  * (rd_result[npairs]). grad_w is float[m] in edge-list order, accumulated in

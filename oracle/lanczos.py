@@ -192,8 +192,8 @@ def tridiag_matrix(alpha, beta) -> np.ndarray:
 
 
 def potentials_lanczos(g, s: int, t: int, run: LanczosRun, d) -> np.ndarray:
-    """phi_hat = sqrt(1/d_s + 1/d_t) D^{-1/2} V (I - T)^{-1} e_1 (Algorithm 5,
-    line 1), from a run made with keep_vectors=True."""
+    """phi_hat = sqrt(1/d_s + 1/d_t) D^{-1/2} V (I - T)^{-1} e_1, the potential
+    estimate of Algorithm 5, from a run made with keep_vectors=True."""
     k = run.k
     c = 1.0 / d[s] + 1.0 / d[t]
     T = tridiag_matrix(run.alpha[:k], run.beta[:k])

@@ -4,7 +4,7 @@ differentiable function of the edge weights.
 forward(w): writes the weights into the graph handle (rd_set_weights) and
 runs the batched Lanczos iteration (rd_query_batch) for the pairs.
 backward(g): rd_grad_edges, which re-runs the iteration and accumulates the
-potentials phi = L^+ (e_s - e_t) (Algorithm 5, line 1) to form
+potentials phi = L^+ (e_s - e_t) (estimated as in Algorithm 5) to form
 dL/dw_e = -sum_p g_p (phi_p(u) - phi_p(v))^2.
 
 This is the derivative of the exact r(s,t) evaluated at the Lanczos

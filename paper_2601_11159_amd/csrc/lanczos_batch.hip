@@ -81,6 +81,8 @@ struct ColCtrl {
   int32_t prev_sparse;  // the previous vector is q_1 (vs at s, vt at t, zero elsewhere)
   int32_t upd_sparse;   // the same, for the update of the current iteration
   int32_t hslot;        // harvest slot of the finished potential (-1: none)
+  int32_t plist;        // 1 + list id: the previous vector is q_2 of a sparse second
+                        // iteration, held in that list (the product reads zeros for it)
 };
 
 template <typename VT, int N>
@@ -369,6 +371,8 @@ struct RunParams {
   int32_t reorth;
   int32_t gmode;          // GRAD_NONE, GRAD_GROUPS or GRAD_HARVEST
   const double *grad_r;   // harvest mode: weight of each pair (nullptr: ones)
+  int32_t s2;             // sparse second iterations on
+  int64_t s2_ecap;        // at most this many scatter entries per column
 };
 
 __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
@@ -917,30 +921,85 @@ __global__ __launch_bounds__(COL_THREADS) void k_beta(const double *__restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sparse second iteration. After the sparse first iteration a refilled column
+// holds w_1 on S = N(s) u N(t) u {s, t}, so q_2 = w_1 / beta_2 has that support
+// and y_2 = D^{-1} W q_2 - beta_2 q_1 lives on N(S), which contains S. Each
+// adjacency entry (u in S, v in N(u)) adds w_uv w_1[u] / d_v to the sum of v
+// and 1 to its count, packed in one 64-bit fixed-point word (sum << 16 | count):
+// integer addition does not depend on the order, so the sums, and the run,
+// are the same every time. The entry whose add found a zero count owns the
+// node (an ownership bit per entry). alpha_2 comes from the sums on S. Each
+// owner writes y_2[v] into the column, adds d_v y_2[v]^2 to ||w_2||_D^2 (in
+// fixed point, so the order of the adds does not matter) and clears the word;
+// a pass over S subtracts alpha_2 q_2 there and corrects the norm.
+// The column joins the dense iterations at i = 3; that product reads zeros for
+// q_2, and k_s2_prev adds its term from the list of S afterwards.
+// ---------------------------------------------------------------------------
+constexpr int S2_PIECE = 256;           // scatter entries of one row per wavefront step
+constexpr int32_t S2_LCAP_MAX = 65535;  // list slots per column at most (deg_s + deg_t + 2),
+                                        // so a count (at most |S|) fits 16 bits
+constexpr int S2_CNT_BITS = 16;
+constexpr double S2_ENTRY_NS = 0.125;  // measured cost of the sparse step per scatter entry (MI355X)
+constexpr double S2_BETA_UNIT = 0x1p58;  // fixed-point units of the ||w_2||^2 terms (<= 1)
+constexpr double S2_BETA_SUB = 0x1p32;   // second word: 2^-90
+
+struct S2Col {
+  int64_t E;       // scatter entries of the current step (0: none)
+  int32_t L;       // list slots of the column's current list (deg_s + deg_t + 2)
+  int32_t nch;     // pieces: rows of the list cut into S2_PIECE entries
+  uint32_t pad;
+  int32_t sexp;    // the sums are kept in units of 2^-sexp
+  double alpha;    // alpha_2
+  unsigned long long bhi, blo;  // ||w_2||_D^2 in units of 2^-58 (two's complement) and 2^-90
+};
+
 // First iteration of every refilled column from the adjacency rows of s and t
 // (block j: column j). Writes w_1 into column j of W (zeroed by k_update),
 // completes iteration 1 of the column's scalars, and arms the next product to
 // read the previous vector q_1 analytically. GRAD: p_1 = q_1, x_1 = q_1/delta_1.
+// s2: also the list of S (slot, node, stored w_1) with the exclusive prefix
+// sums of the rows' piece counts, and the sparse second step when its scatter
+// has at most s2_ecap entries.
 template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(256) void k_first_batch(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     const double *__restrict__ w64, const double *__restrict__ deg, VT *__restrict__ W,
     LzState *__restrict__ st, ColCtrl *__restrict__ ctrl, VT *__restrict__ P, VT *__restrict__ X,
-    const int32_t *__restrict__ active) {
+    const int32_t *__restrict__ active, int32_t s2, int64_t s2_ecap, int32_t lcap,
+    int32_t *__restrict__ Lu, double *__restrict__ Lw, int64_t *__restrict__ Lp,
+    S2Col *__restrict__ s2c, int32_t *__restrict__ pslot, int64_t pcap) {
   if (*active == 0) return;
   const int j = blockIdx.x;
   if (!starts_pair(ctrl[j].mode)) return;
   __shared__ double sm[256 / 64 + 2];
+  __shared__ int64_t wsum[256 / 64];
   __shared__ LzState S0;
+  __shared__ int32_t take;
   if (threadIdx.x == 0) S0 = st[j];
   __syncthreads();
   const int32_t s = S0.s, t = S0.t;
+  const int32_t L = (row_ptr[s + 1] - row_ptr[s]) + (row_ptr[t + 1] - row_ptr[t]) + 2;
+  const bool lst = !GRAD && s2 && L <= lcap;
+  int32_t *lu = Lu + (size_t)j * lcap;
+  double *lw = Lw + (size_t)j * lcap;
+  int64_t *lp = Lp + (size_t)j * (lcap + 1);
+  if (lst) {
+    for (int32_t k = threadIdx.x; k < L; k += blockDim.x) lu[k] = -1;
+    __syncthreads();
+  }
+  double mx = 0.0;
   double a1, bb;
   first_iteration(
       row_ptr, col, w64, deg, s, t, S0.c,
-      [&](int32_t u, double val) {
+      [&](int32_t u, double val, int32_t pos) {
         const VT x = (VT)val;
         W[(size_t)u * B + j] = x;
+        if (lst) {
+          lu[pos] = u;
+          lw[pos] = (double)x;
+          mx = fmax(mx, fabs((double)x));
+        }
         return (double)x;
       },
       sm, a1, bb);
@@ -960,6 +1019,7 @@ __global__ __launch_bounds__(256) void k_first_batch(
     }
     cc.mode = COL_RUN;
     cc.coef = 0.0;
+    cc.plist = 0;
     if (S.status == LZ_RUNNING) {
       cc.sig = S.sig_cur;     // 1 / beta_2
       cc.pc = S.prev_coef;    // beta_2 (q_1 is stored with scale 1)
@@ -971,12 +1031,420 @@ __global__ __launch_bounds__(256) void k_first_batch(
     }
     st[j] = S;
     ctrl[j] = cc;
+    take = lst && S.status == LZ_RUNNING;
+  }
+  __syncthreads();
+  if (!take) return;
+  // exclusive prefix sums of the piece counts of the list's rows (empty
+  // slots: 0), and the number of scatter entries
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t carry = 0, ent = 0;
+  for (int32_t base = 0; base < L; base += 256) {
+    const int32_t k = base + threadIdx.x;
+    int64_t d = 0;
+    if (k < L) {
+      const int32_t u = lu[k];
+      if (u >= 0) {
+        const int32_t len = row_ptr[u + 1] - row_ptr[u];
+        d = (len + S2_PIECE - 1) / S2_PIECE;
+        ent += len;
+      }
+    }
+    int64_t x = d;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int64_t before = carry, tot = 0;
+    for (int w = 0; w < 256 / 64; ++w) {
+      if (w < wid) before += wsum[w];
+      tot += wsum[w];
+    }
+    if (k < L) lp[k] = before + x - d;
+    __syncthreads();
+    carry += tot;
+  }
+  // the largest |w_1| sets the fixed-point unit
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  ent = wave_sum(ent);
+  if (lane == 0) {
+    sm[wid] = mx;
+    wsum[wid] = ent;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lp[L] = carry;
+    ent = 0;
+    for (int w = 0; w < 256 / 64; ++w) {
+      mx = fmax(mx, sm[w]);
+      ent += wsum[w];
+    }
+    S2Col c = s2c[j];
+    c.L = L;
+    c.E = 0;
+    // (at most 2^22 pieces per column keeps the piece offsets of 256 columns in int32)
+    if (ent > 0 && ent <= s2_ecap && carry <= (1 << 22) && mx > 0.0) {
+      // |sum_u w_uv w_1[u] / d_v| <= max |w_1| < 2^e: units of 2^(e - 46) keep
+      // every sum below 2^46, which leaves 16 bits of the word for the count
+      int e;
+      (void)frexp(mx, &e);
+      c.E = ent;
+      c.nch = (int32_t)carry;
+      c.sexp = 46 - e;
+      c.bhi = c.blo = 0;
+    }
+    s2c[j] = c;
+    take = c.E > 0;
+  }
+  __syncthreads();
+  if (!take) return;
+  // the list slot of every piece
+  int32_t *ps = pslot + (size_t)j * pcap;
+  for (int32_t k = threadIdx.x; k < L; k += blockDim.x)
+    for (int64_t r = lp[k]; r < lp[k + 1]; ++r) ps[r] = k;
+}
+
+// Piece offsets of the columns taking the sparse step: cpre[j] = sum of nch
+// over the columns before j (one thread, B <= 256).
+__global__ void k_s2_plan(int32_t B, const S2Col *__restrict__ s2c, int32_t *__restrict__ cpre,
+                          const int32_t *__restrict__ active) {
+  if (*active == 0 || threadIdx.x != 0) return;
+  int32_t acc = 0;
+  for (int c = 0; c < B; ++c) {
+    cpre[c] = acc;
+    if (s2c[c].E > 0) acc += s2c[c].nch;
+  }
+  cpre[B] = acc;
+}
+
+// Column of piece c (the last j with cpre[j] <= c; cpre[0] = 0 <= c < cpre[B]).
+__device__ __forceinline__ int32_t s2_column(const int32_t *cpre, int32_t B, int32_t c) {
+  int32_t lo = 0, hi = B;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (cpre[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// A global piece c: its column j, list slot k (holding u) and the row
+// entries [pb, pe) it covers. cp: the piece offsets (in LDS).
+struct S2Piece {
+  int32_t j, k, u, pb, pe;
+};
+__device__ __forceinline__ S2Piece s2_piece(const int32_t *cp, int32_t B, int32_t c, int32_t lcap,
+                                            int64_t pcap, const int32_t *__restrict__ pslot,
+                                            const int32_t *__restrict__ Lu, const int64_t *__restrict__ Lp,
+                                            const int32_t *__restrict__ row_ptr) {
+  S2Piece q;
+  q.j = s2_column(cp, B, c);
+  const int32_t r = c - cp[q.j];
+  q.k = pslot[(size_t)q.j * pcap + r];
+  q.u = Lu[(size_t)q.j * lcap + q.k];
+  const int64_t first = Lp[(size_t)q.j * (lcap + 1) + q.k];
+  q.pb = row_ptr[q.u] + (int32_t)(r - first) * S2_PIECE;
+  q.pe = min(q.pb + S2_PIECE, row_ptr[q.u + 1]);
+  return q;
+}
+
+// the sum and the count of a packed word
+__device__ __forceinline__ double s2_sum(unsigned long long a, double inv_unit) {
+  return (double)((long long)a >> S2_CNT_BITS) * inv_unit;
+}
+__device__ __forceinline__ bool s2_count_is_zero(unsigned long long a) {
+  return (a & ((1ull << S2_CNT_BITS) - 1)) == 0;
+}
+
+// The scatter, one row piece per wavefront: piece r of column j covers
+// entries q*S2_PIECE .. of the row of the list slot k holding u (q = r - lp[k]);
+// each entry (u, v) adds w_uv w_1[u] / d_v, in units of 2^-sexp, and a count
+// of 1 to the word acc[j][v] (two's complement in unsigned 64-bit words). Bit
+// `lane` of own[c][i] marks the entry pb + lane + 64 i of global piece c whose
+// add found the count at zero: one entry per node.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_s2_scatter(
+    int32_t B, int32_t n, const int32_t *__restrict__ cpre, const S2Col *__restrict__ s2c, int32_t lcap,
+    int64_t pcap, const int32_t *__restrict__ pslot, const int32_t *__restrict__ Lu,
+    const double *__restrict__ Lw, const int64_t *__restrict__ Lp, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col, const double *__restrict__ w64, const double *__restrict__ deg,
+    unsigned long long *__restrict__ acc, unsigned long long *__restrict__ own,
+    const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  constexpr int NI = S2_PIECE / 64;
+  __shared__ int32_t cp[257];
+  for (int i = threadIdx.x; i <= B; i += blockDim.x) cp[i] = cpre[i];
+  __syncthreads();
+  const int32_t total = cp[B];
+  const int lane = threadIdx.x & 63;
+  const int32_t nwv = gridDim.x * (256 / 64);
+  for (int32_t c = blockIdx.x * (256 / 64) + (threadIdx.x >> 6); c < total; c += nwv) {
+    const S2Piece q = s2_piece(cp, B, c, lcap, pcap, pslot, Lu, Lp, row_ptr);
+    const double wu = Lw[(size_t)q.j * lcap + q.k];
+    const double unit = ldexp(1.0, s2c[q.j].sexp);
+    unsigned long long *aj = acc + (size_t)q.j * n;
+    // the piece's entries: every load first, then every add
+    int32_t v[NI];
+    double f[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int32_t p = q.pb + lane + 64 * i;
+      v[i] = p < q.pe ? col[p] : -1;
+      f[i] = (WEIGHTED && p < q.pe) ? w64[p] : 1.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      if (v[i] >= 0) f[i] *= wu / deg[v[i]];
+    unsigned long long old[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      old[i] = 1ull;  // not an owner
+      if (v[i] >= 0) {
+        const long long fx = llrint(f[i] * unit);
+        old[i] = atomicAdd(aj + v[i], ((unsigned long long)fx << S2_CNT_BITS) + 1ull);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const unsigned long long m = __ballot(s2_count_is_zero(old[i]));
+      if (lane == 0) own[(size_t)c * NI + i] = m;
+    }
+  }
+}
+
+// alpha_2 = <y_2, q_2>_D over S (block j: column j, fixed order), then the
+// column's scalar step.
+__global__ __launch_bounds__(256) void k_s2_alpha(int32_t n, S2Col *__restrict__ s2c, int32_t lcap,
+                                                  const int32_t *__restrict__ Lu, const double *__restrict__ Lw,
+                                                  const double *__restrict__ deg,
+                                                  const unsigned long long *__restrict__ acc,
+                                                  LzState *__restrict__ st, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  const int j = blockIdx.x;
+  if (s2c[j].E == 0) return;
+  __shared__ double sm[256 / 64];
+  const LzState S0 = st[j];
+  const int32_t L = s2c[j].L;
+  const double inv = ldexp(1.0, -s2c[j].sexp);
+  const double sig = S0.sig_cur, beta = S0.beta;  // 1/beta_2, beta_2
+  const double rc = 1.0 / sqrt(S0.c);
+  const double q1s = rc / deg[S0.s], q1t = -rc / deg[S0.t];
+  const int32_t *lu = Lu + (size_t)j * lcap;
+  const double *lw = Lw + (size_t)j * lcap;
+  const unsigned long long *aj = acc + (size_t)j * n;
+  double a = 0.0;
+  for (int32_t k = threadIdx.x; k < L; k += blockDim.x) {
+    const int32_t u = lu[k];
+    if (u < 0) continue;
+    const double q1 = u == S0.s ? q1s : (u == S0.t ? q1t : 0.0);
+    const double y = sig * s2_sum(aj[u], inv) - beta * q1;
+    a += deg[u] * y * (sig * lw[k]);
+  }
+  a = block_sum(a, sm);
+  if (threadIdx.x == 0) {
+    LzState S = S0;
+    scalar_after_alpha(S, a, nullptr, nullptr);
+    s2c[j].alpha = a;
+    st[j] = S;
+  }
+}
+
+// The owner of each node v of N(S) writes y_2[v] into column j of W, adds
+// d_v y_2[v]^2 to the fixed-point norm and clears the node's word (a column
+// that stopped at alpha_2 only clears).
+template <typename VT, int B>
+__global__ __launch_bounds__(256) void k_s2_write(
+    int32_t n, const int32_t *__restrict__ cpre, S2Col *__restrict__ s2c, int32_t lcap, int64_t pcap,
+    const int32_t *__restrict__ pslot, const int32_t *__restrict__ Lu, const int64_t *__restrict__ Lp,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ deg,
+    unsigned long long *__restrict__ acc, const unsigned long long *__restrict__ own,
+    const LzState *__restrict__ st, VT *__restrict__ W, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  constexpr int NI = S2_PIECE / 64;
+  __shared__ int32_t cp[257];
+  for (int i = threadIdx.x; i <= B; i += blockDim.x) cp[i] = cpre[i];
+  __syncthreads();
+  const int32_t total = cp[B];
+  const int lane = threadIdx.x & 63;
+  const int32_t nwv = gridDim.x * (256 / 64);
+  // one row piece per wavefront, as in k_s2_scatter
+  for (int32_t c = blockIdx.x * (256 / 64) + (threadIdx.x >> 6); c < total; c += nwv) {
+    const S2Piece q = s2_piece(cp, B, c, lcap, pcap, pslot, Lu, Lp, row_ptr);
+    const int32_t j = q.j;
+    const LzState &S = st[j];
+    const bool running = S.status == LZ_RUNNING;
+    const double inv = ldexp(1.0, -s2c[j].sexp);
+    const double sig = S.sig_cur, beta = S.beta;
+    const int32_t s = S.s, t = S.t;
+    const double rc = 1.0 / sqrt(S.c);
+    const double q1s = rc / deg[s], q1t = -rc / deg[t];
+    unsigned long long *aj = acc + (size_t)j * n;
+    // the owned entries: every load first
+    int32_t v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int32_t p = q.pb + lane + 64 * i;
+      const bool mine = p < q.pe && ((own[(size_t)c * NI + i] >> lane) & 1ull);
+      v[i] = mine ? col[p] : -1;
+    }
+    unsigned long long a[NI];
+    double dv[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      a[i] = 0ull;
+      dv[i] = 0.0;
+      if (v[i] >= 0) {
+        a[i] = aj[v[i]];
+        dv[i] = deg[v[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      if (v[i] >= 0) aj[v[i]] = 0ull;
+    // each node's term of the norm in fixed point on its own, so the total
+    // does not depend on which entry owned the node
+    unsigned long long hi = 0, lo = 0;
+    if (running) {
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        if (v[i] < 0) continue;
+        const double q1 = v[i] == s ? q1s : (v[i] == t ? q1t : 0.0);
+        const VT x = (VT)(sig * s2_sum(a[i], inv) - beta * q1);
+        W[(size_t)v[i] * B + j] = x;
+        const double th = dv[i] * (double)x * (double)x * S2_BETA_UNIT;
+        const double fh = floor(th);
+        hi += (unsigned long long)fh;
+        lo += (unsigned long long)((th - fh) * S2_BETA_SUB);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      hi += __shfl_xor(hi, off, 64);
+      lo += __shfl_xor(lo, off, 64);
+    }
+    if (lane == 0 && running && (hi | lo)) {
+      atomicAdd(&s2c[j].bhi, hi);
+      atomicAdd(&s2c[j].blo, lo);
+    }
+  }
+}
+
+// On S (block j: column j, fixed order): w_2 = y_2 - alpha_2 q_2 in place of the
+// y_2 that k_s2_write stored (S is inside N(S)), and the norm corrected by the
+// difference.
+template <typename VT, int B>
+__global__ __launch_bounds__(256) void k_s2_fix(int32_t n, S2Col *__restrict__ s2c, int32_t lcap,
+                                                const int32_t *__restrict__ Lu, const double *__restrict__ Lw,
+                                                const double *__restrict__ deg, const LzState *__restrict__ st,
+                                                VT *__restrict__ W, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  const int j = blockIdx.x;
+  if (s2c[j].E == 0 || st[j].status != LZ_RUNNING) return;
+  __shared__ double sm[256 / 64];
+  const LzState &S = st[j];
+  const int32_t L = s2c[j].L;
+  const double alpha = s2c[j].alpha;
+  const double sig = S.sig_cur;
+  const int32_t *lu = Lu + (size_t)j * lcap;
+  const double *lw = Lw + (size_t)j * lcap;
+  double d = 0.0;
+  for (int32_t k = threadIdx.x; k < L; k += blockDim.x) {
+    const int32_t u = lu[k];
+    if (u < 0) continue;
+    const size_t ix = (size_t)u * B + j;
+    const double x0 = (double)W[ix];  // y_2[u] as k_s2_write stored it
+    const VT x = (VT)(x0 - alpha * (sig * lw[k]));
+    W[ix] = x;
+    d += deg[u] * ((double)x * (double)x - x0 * x0);
+  }
+  d = block_sum(d, sm);
+  if (threadIdx.x == 0) {
+    // the norm's two words take the signed correction: hi floor, lo >= 0
+    const double th = d * S2_BETA_UNIT;
+    const double fh = floor(th);
+    s2c[j].bhi += (unsigned long long)(long long)fh;
+    s2c[j].blo += (unsigned long long)((th - fh) * S2_BETA_SUB);
+  }
+}
+
+// beta_3 of every column that took the sparse step, its scales for the dense
+// iterations, and the previous-vector list (one thread per column).
+__global__ void k_s2_beta(int32_t B, S2Col *__restrict__ s2c, LzState *__restrict__ st,
+                          ColCtrl *__restrict__ ctrl, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  const int j = threadIdx.x;
+  if (j >= B || s2c[j].E == 0) return;
+  S2Col c = s2c[j];
+  const double bb = ldexp((double)(long long)c.bhi, -58) + ldexp((double)c.blo, -90);
+  c.bhi = c.blo = 0;
+  c.E = 0;
+  s2c[j] = c;
+  LzState S = st[j];
+  ColCtrl cc = ctrl[j];
+  if (S.status == LZ_RUNNING) scalar_after_beta(S, bb, nullptr);
+  if (S.status == LZ_RUNNING) {
+    cc.sig = S.sig_cur;   // 1 / beta_3 (W holds w_2)
+    cc.pc = S.prev_coef;  // beta_3 / beta_2: the list holds w_1 = beta_2 q_2
+    cc.prev_sparse = 1;   // the product reads zeros for q_2 ...
+    cc.vs = cc.vt = 0.0;
+    cc.plist = j + 1;     // ... and k_s2_prev adds its term
+  } else {
+    cc.sig = 0.0;  // stopped at the second iteration: retired by the next control step
+    cc.pc = 0.0;
+    cc.prev_sparse = 0;
+    cc.plist = 0;
+  }
+  st[j] = S;
+  ctrl[j] = cc;
+}
+
+// After the product of a column whose previous vector is a listed q_2:
+// Y -= pc w_1 on S, and the change of <Y, q_i>_D into partial slot `slot`
+// (zero for the other columns). Block j: column j.
+template <typename VT, int B>
+__global__ __launch_bounds__(256) void k_s2_prev(const S2Col *__restrict__ s2c, int32_t lcap,
+                                                 const int32_t *__restrict__ Lu, const double *__restrict__ Lw,
+                                                 const double *__restrict__ deg, const VT *__restrict__ Ucur,
+                                                 VT *__restrict__ Y, ColCtrl *__restrict__ ctrl,
+                                                 double *__restrict__ part, int32_t ldp, int32_t slot,
+                                                 const int32_t *__restrict__ active) {
+  if (*active == 0) return;
+  __shared__ double sm[256 / 64];
+  const int j = blockIdx.x;
+  const int32_t pl = ctrl[j].plist;
+  double a = 0.0;
+  if (pl > 0) {
+    const int32_t id = pl - 1;
+    const int32_t L = s2c[id].L;
+    const VT pc = (VT)ctrl[j].pc;
+    const double sg = (double)(VT)ctrl[j].sig;
+    const int32_t *lu = Lu + (size_t)id * lcap;
+    const double *lw = Lw + (size_t)id * lcap;
+    for (int32_t k = threadIdx.x; k < L; k += blockDim.x) {
+      const int32_t u = lu[k];
+      if (u < 0) continue;
+      const size_t ix = (size_t)u * B + j;
+      const VT old = Y[ix];
+      const VT nv = old - pc * (VT)lw[k];
+      Y[ix] = nv;
+      a += deg[u] * ((double)nv - (double)old) * (sg * (double)Ucur[ix]);
+    }
+  }
+  a = block_sum(a, sm);
+  if (threadIdx.x == 0) {
+    part[(size_t)j * ldp + slot] = a;
+    if (pl > 0) ctrl[j].plist = 0;
   }
 }
 
 __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__restrict__ ctrl,
-                              int32_t *__restrict__ qstate) {
+                              int32_t *__restrict__ qstate, S2Col *__restrict__ s2c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s2c && j < B) {
+    s2c[j].E = 0;
+    s2c[j].bhi = s2c[j].blo = 0;
+  }
   if (j < B) {
     LzState S;
     state_start(S, 0, 0, 0.0, 0.0, 0, 0, 4, 0, -1);
@@ -1057,9 +1525,22 @@ struct BatchWork {
   int32_t *qstate_host = nullptr;  // pinned
   int32_t *flag = nullptr;
   int32_t *cmap = nullptr;  // [128] source columns of a compaction
+  // sparse second iterations: per column, a fixed-point word per node and the
+  // list of S with the prefix sums of its rows' piece counts
+  int32_t s2_slots = 0, s2_lcap = 0;
+  unsigned long long *s2_acc = nullptr;  // [s2_slots][n]
+  int32_t *s2_lu = nullptr;              // [s2_slots][s2_lcap]
+  double *s2_lw = nullptr;               // [s2_slots][s2_lcap]
+  int64_t *s2_lp = nullptr;              // [s2_slots][s2_lcap + 1]
+  unsigned long long *s2_own = nullptr;  // ownership bits: [s2_slots * s2_pcap][S2_PIECE / 64]
+  int32_t *s2_pslot = nullptr;           // list slot of every piece: [s2_slots][s2_pcap]
+  int64_t s2_pcap = 0;                   // row pieces per column at most
+  S2Col *s2c = nullptr;                  // [256]
+  int32_t *s2_cpre = nullptr;            // [257]
   // autotune cache: chosen width and schedule per precision
   int32_t tuned[2] = {0, 0};
   int32_t tuned_wave[2] = {0, 0}, tuned_long[2] = {0, 0};
+  double tuned_col_ms[2] = {0.0, 0.0};  // product time per column at that width and schedule
 };
 
 void batch_free(rd_graph g) {
@@ -1082,6 +1563,14 @@ void batch_free(rd_graph g) {
   dev_free(bw->qstate);
   dev_free(bw->flag);
   dev_free(bw->cmap);
+  dev_free(bw->s2_acc);
+  dev_free(bw->s2_own);
+  dev_free(bw->s2_pslot);
+  dev_free(bw->s2_lu);
+  dev_free(bw->s2_lw);
+  dev_free(bw->s2_lp);
+  dev_free(bw->s2c);
+  dev_free(bw->s2_cpre);
   if (bw->qstate_host) (void)hipHostFree(bw->qstate_host);
   delete bw;
   g->batch = nullptr;
@@ -1134,7 +1623,8 @@ static void build_schedule(rd_graph g, BatchWork *bw, int32_t wave_nnz, int32_t 
   // the number of partial sums per column is fixed
   bw->grid_short = std::max(1, std::min<int32_t>(cus * 8, (bw->nwi + 3) / 4));
   bw->grid_upd = std::max(1, std::min<int32_t>(cus * 8, cdiv(g->n, 64)));
-  bw->ldp = std::max(bw->grid_short + bw->nlong, bw->grid_upd);
+  // one slot more than the products write: the sparse-step correction
+  bw->ldp = std::max(bw->grid_short + bw->nlong + 1, bw->grid_upd);
   bw->wave_nnz = wave_nnz;
   bw->long_deg = long_deg;
 }
@@ -1152,8 +1642,50 @@ static BatchWork *batch_get(rd_graph g) {
   bw->qstate = (int32_t *)dev_alloc(8 * sizeof(int32_t));
   bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
   bw->cmap = (int32_t *)dev_alloc(128 * sizeof(int32_t));
+  bw->s2c = (S2Col *)dev_alloc(256 * sizeof(S2Col));
+  RD_HIP(hipMemset(bw->s2c, 0, 256 * sizeof(S2Col)));
+  bw->s2_cpre = (int32_t *)dev_alloc(257 * sizeof(int32_t));
   RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 4 * sizeof(int32_t), hipHostMallocDefault));
   return bw;
+}
+
+// Buffers of the sparse second iterations for B columns. Returns false (the
+// run then uses dense second iterations) when the per-node arrays would take
+// more than S2_MAX_BYTES.
+constexpr size_t S2_MAX_BYTES = (size_t)24 << 30;
+static bool s2_reserve(rd_graph g, BatchWork *bw, int32_t B, hipStream_t st) {
+  if (B <= bw->s2_slots) return true;
+  const size_t per = (size_t)g->n * sizeof(unsigned long long);
+  if (per * B > S2_MAX_BYTES) return false;
+  dev_free(bw->s2_acc);
+  dev_free(bw->s2_own);
+  dev_free(bw->s2_pslot);
+  dev_free(bw->s2_lu);
+  dev_free(bw->s2_lw);
+  dev_free(bw->s2_lp);
+  bw->s2_acc = nullptr;
+  bw->s2_own = nullptr;
+  bw->s2_pslot = nullptr;
+  bw->s2_lu = nullptr;
+  bw->s2_lw = nullptr;
+  bw->s2_lp = nullptr;
+  bw->s2_slots = 0;
+  const int32_t lcap = (int32_t)std::min<int64_t>(2 * (int64_t)g->max_deg + 2, S2_LCAP_MAX);
+  bw->s2_acc = (unsigned long long *)dev_alloc((size_t)B * g->n * sizeof(unsigned long long));
+  bw->s2_lu = (int32_t *)dev_alloc((size_t)B * lcap * sizeof(int32_t));
+  bw->s2_lw = (double *)dev_alloc((size_t)B * lcap * sizeof(double));
+  bw->s2_lp = (int64_t *)dev_alloc((size_t)B * (lcap + 1) * sizeof(int64_t));
+  // a column's pieces: at most one per list slot plus entries / S2_PIECE, and
+  // at most s2_ecap <= nnz * 8 / 128 entries
+  bw->s2_pcap = lcap + g->nnz * 8 / 128 / S2_PIECE + 1;
+  bw->s2_own = (unsigned long long *)dev_alloc((size_t)B * bw->s2_pcap * (S2_PIECE / 64) *
+                                               sizeof(unsigned long long));
+  bw->s2_pslot = (int32_t *)dev_alloc((size_t)B * bw->s2_pcap * sizeof(int32_t));
+  RD_HIP(hipMemsetAsync(bw->s2_acc, 0, (size_t)B * g->n * sizeof(unsigned long long), st));
+  RD_HIP(hipMemsetAsync(bw->s2c, 0, 256 * sizeof(S2Col), st));
+  bw->s2_lcap = lcap;
+  bw->s2_slots = B;
+  return true;
 }
 
 static void batch_reserve(rd_graph g, BatchWork *bw, int32_t B, size_t elem) {
@@ -1214,10 +1746,39 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Upr
 }
 
 template <typename VT, int B, bool GRAD>
-static void launch_first(rd_graph g, BatchWork *bw, VT *W, hipStream_t st) {
+static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm, hipStream_t st) {
+  const int32_t *active = bw->qstate + 1;
+  const bool s2 = !GRAD && prm.s2;
   hipLaunchKernelGGL((k_first_batch<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->row_ptr, g->col,
                      (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (VT *)bw->P, (VT *)bw->Xp,
-                     bw->qstate + 1);
+                     active, s2 ? 1 : 0, prm.s2_ecap, bw->s2_lcap, bw->s2_lu, bw->s2_lw, bw->s2_lp, bw->s2c,
+                     bw->s2_pslot, bw->s2_pcap);
+  if (!s2) return;
+  const int32_t grid = 2048;  // 8192 wavefronts over the row pieces
+  hipLaunchKernelGGL(k_s2_plan, dim3(1), dim3(64), 0, st, B, (const S2Col *)bw->s2c, bw->s2_cpre, active);
+  if (g->unit)
+    hipLaunchKernelGGL(k_s2_scatter<false>, dim3(grid), dim3(256), 0, st, B, g->n,
+                       (const int32_t *)bw->s2_cpre, (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
+                       (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw,
+                       (const int64_t *)bw->s2_lp,
+                       g->row_ptr, g->col, (const double *)nullptr, g->deg, bw->s2_acc, bw->s2_own, active);
+  else
+    hipLaunchKernelGGL(k_s2_scatter<true>, dim3(grid), dim3(256), 0, st, B, g->n,
+                       (const int32_t *)bw->s2_cpre, (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
+                       (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw,
+                       (const int64_t *)bw->s2_lp,
+                       g->row_ptr, g->col, (const double *)g->w64, g->deg, bw->s2_acc, bw->s2_own, active);
+  hipLaunchKernelGGL(k_s2_alpha, dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
+                     (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg,
+                     (const unsigned long long *)bw->s2_acc, bw->st, active);
+  hipLaunchKernelGGL((k_s2_write<VT, B>), dim3(grid), dim3(256), 0, st, g->n, (const int32_t *)bw->s2_cpre,
+                     bw->s2c, bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot,
+                     (const int32_t *)bw->s2_lu, (const int64_t *)bw->s2_lp, g->row_ptr, g->col, g->deg,
+                     bw->s2_acc, (const unsigned long long *)bw->s2_own, (const LzState *)bw->st, W, active);
+  hipLaunchKernelGGL((k_s2_fix<VT, B>), dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
+                     (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, (const LzState *)bw->st,
+                     W, active);
+  hipLaunchKernelGGL(k_s2_beta, dim3(1), dim3(256), 0, st, B, bw->s2c, bw->st, bw->ctrl, active);
 }
 
 // The three vector blocks of a run: q_{i-1}, q_i and the block the next
@@ -1244,8 +1805,15 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
     launch_spmm<VT, B, false>(g, bw, Ucur, Uprev, Y, st, active, prof);
   else
     launch_spmm<VT, B, true>(g, bw, Ucur, Uprev, Y, st, active, prof);
-  hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp,
-                     bw->grid_short + bw->nlong, bw->colsum, active);
+  int32_t np = bw->grid_short + bw->nlong;
+  if (!GRAD && prm.s2) {
+    hipLaunchKernelGGL((k_s2_prev<VT, B>), dim3(B), dim3(256), 0, st, (const S2Col *)bw->s2c, bw->s2_lcap,
+                       (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, Ucur, Y, bw->ctrl,
+                       bw->part, bw->ldp, np, active);
+    np += 1;
+  }
+  hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, np, bw->colsum,
+                     active);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
                      (const double *)bw->colsum, prm, ps, pt, g->deg, out, bw->qstate, prm.gmode,
                      prm.grad_r, bw->cw);
@@ -1271,7 +1839,7 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
   }
   hipLaunchKernelGGL(k_beta, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
                      bw->st, bw->ctrl, active);
-  launch_first<VT, B, GRAD>(g, bw, Y, st);
+  launch_first<VT, B, GRAD>(g, bw, Y, prm, st);
 }
 
 // Tail compaction: the running columns of a B-wide run (their q_i and q_{i-1}
@@ -1379,11 +1947,26 @@ static int64_t batch_loop(rd_graph g, BatchWork *bw, RunBufs rb, int32_t npairs,
 // accumulated in bw->Xp (bw->P, bw->Xp zeroed by the caller); no compaction.
 template <typename VT, int B, bool GRAD = false>
 static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
-                           const int32_t *pt, const RunParams &prm, rd_result *out, hipStream_t st,
+                           const int32_t *pt, const RunParams &prm_in, rd_result *out, hipStream_t st,
                            bool prof, bool compact_ok = false) {
   batch_reserve(g, bw, B, sizeof(VT));
+  RunParams prm = prm_in;
   if (prm.reorth > 0) reorth_reserve(bw);
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
+  // sparse second steps (not with re-orthogonalisation or potentials) for
+  // columns whose scatter costs less than the dense iteration it replaces:
+  // the autotuned product time per column (times 1.15 for the update and
+  // reductions around it) over the cost of one scatter entry, else
+  // nnz * size / 256 entries (the two measured optima were nnz * 4 / 512 for
+  // a power-law graph in FP32 and nnz * 8 / 128 for another in FP64)
+  prm.s2 = !GRAD && prm.s2 && prm.reorth == 0 && s2_reserve(g, bw, B, st);
+  const int pi = sizeof(VT) == 8 ? RD_F64 : RD_F32;
+  if (bw->tuned[pi] == B && bw->tuned_col_ms[pi] > 0.0)
+    prm.s2_ecap = (int64_t)(bw->tuned_col_ms[pi] * 1.15 * 1e6 / S2_ENTRY_NS);
+  else
+    prm.s2_ecap = g->nnz * (int64_t)sizeof(VT) / 256;
+  prm.s2_ecap = std::min<int64_t>(std::max<int64_t>(prm.s2_ecap, 1), g->nnz * 8 / 128);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate,
+                     bw->s2c);
   // fill the slots: control with every column idle pops the first B pairs,
   // then the update writes their start vectors (and zeros elsewhere)
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl,
@@ -1393,7 +1976,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
                      bw->part, bw->ldp, bw->qstate + 1, (VT *)nullptr, (VT *)nullptr, 0,
                      (double *)nullptr, (VT *)nullptr);
-  launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], st);
+  launch_first<VT, B, GRAD>(g, bw, (VT *)bw->X[0], prm, st);
   RD_HIP(hipGetLastError());
   // every column starts from the sparse q_1, so the first product reads no
   // previous vector; X[0] holds w_1
@@ -1524,7 +2107,8 @@ static void grad_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, 
 template <typename VT, int B>
 static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
   batch_reserve(g, bw, B, sizeof(VT));
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, B, bw->st, bw->ctrl, bw->qstate,
+                     bw->s2c);
   hipLaunchKernelGGL((k_update<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
                      bw->part, bw->ldp, bw->qstate + 3, (VT *)nullptr, (VT *)nullptr, 0,
@@ -1590,10 +2174,13 @@ static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npair
         std::istringstream in(line);
         std::string k;
         int32_t B = 0, wv = 0, ld = 0;
+        double cm = 0.0;
         if ((in >> k >> B >> wv >> ld) && k == key && valid_width(B) && wv >= 32 && ld >= 64) {
+          if (!(in >> cm) || !(cm > 0.0)) cm = 0.0;  // optional fifth field
           bw->tuned[prec] = B;
           bw->tuned_wave[prec] = wv;
           bw->tuned_long[prec] = ld;
+          bw->tuned_col_ms[prec] = cm;
         }
       }
     }
@@ -1607,7 +2194,10 @@ static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npair
       for (int32_t B : {32, 64, 128, 256}) {
         if (B > 32 && B / 2 >= npairs) break;  // wider than the work: no gain
         const double per_col = probe(B) / B;
-        if (per_col < best_t) {
+        // a wider block must be clearly faster per column: it also refills
+        // more columns per iteration and leaves a longer tail (on a 4M-node
+        // power-law graph 256 probed within 5% of 64 but ran 5% slower)
+        if (per_col < best_t * 0.95) {
           best_t = per_col;
           best = B;
         }
@@ -1629,9 +2219,11 @@ static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npair
       bw->tuned[prec] = best;
       bw->tuned_wave[prec] = best_wave;
       bw->tuned_long[prec] = best_long;
+      bw->tuned_col_ms[prec] = best_s / best;
       if (path) {
         std::ofstream f(path, std::ios::app);
-        f << key << " " << best << " " << best_wave << " " << best_long << "\n";
+        f << key << " " << best << " " << best_wave << " " << best_long << " " << bw->tuned_col_ms[prec]
+          << "\n";
       }
     }
   }
@@ -1705,6 +2297,7 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
         grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
     } else {
       const bool compact = !(opt.flags & RD_NO_COMPACT);
+      prm.s2 = !(opt.flags & RD_NO_SPARSE2);
       if (opt.precision == RD_F64)
         batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof, compact);
       else

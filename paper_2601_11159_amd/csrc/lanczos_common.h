@@ -160,10 +160,14 @@ __device__ __forceinline__ int32_t row_find(const int32_t *__restrict__ row_ptr,
 // t only: q_1 = (e_s/d_s - e_t/d_t)/sqrt(c) has two non-zeros, so
 // y_1 = D^{-1} W q_1 lives on N(s) u N(t), alpha_1 = <y_1, q_1>_D involves
 // rows s and t alone, and w_1 = y_1 - alpha_1 q_1 lives on N(s) u N(t) u {s, t}.
-// Every entry of w_1 is passed once to store(u, value) (which returns the value
-// as stored, e.g. rounded to FP32); the block returns alpha_1 and
-// ||w_1||_D^2 (summed in a fixed order) in every thread. All threads of the
-// block must call it. `sm` needs blockDim.x/64 + 2 doubles.
+// Every entry of w_1 is passed once to store(u, value, pos) (which returns the
+// value as stored, e.g. rounded to FP32). pos is the entry's slot in a list
+// of deg_s + deg_t + 2 slots (deg_x = row length): entries of row s take their
+// adjacency position, entries of row t not in row s take deg_s + theirs, and
+// s and t, when they are not neighbours, the last two. The slots of row-t
+// entries that are also in row s (and the last two when s ~ t) stay unused.
+// The block returns alpha_1 and ||w_1||_D^2 (summed in a fixed order) in every
+// thread. All threads of the block must call it. `sm` needs blockDim.x/64 + 2 doubles.
 template <typename Store>
 __device__ void first_iteration(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                 const double *__restrict__ w64, const double *__restrict__ deg,
@@ -192,7 +196,7 @@ __device__ void first_iteration(const int32_t *__restrict__ row_ptr, const int32
     if (pt >= 0) val += (w64 ? w64[pt] : 1.0) * q1t;
     val /= deg[u];
     if (u == t) val -= a1 * q1t;
-    const double stored = store(u, val);
+    const double stored = store(u, val, p - row_ptr[s]);
     acc += deg[u] * stored * stored;
   }
   // u in N(t) \ N(s)
@@ -201,13 +205,14 @@ __device__ void first_iteration(const int32_t *__restrict__ row_ptr, const int32
     if (row_find(row_ptr, col, s, u) >= 0) continue;
     double val = (w64 ? w64[p] : 1.0) * q1t / deg[u];
     if (u == s) val -= a1 * q1s;
-    const double stored = store(u, val);
+    const double stored = store(u, val, (row_ptr[s + 1] - row_ptr[s]) + (p - row_ptr[t]));
     acc += deg[u] * stored * stored;
   }
   // s and t themselves when they are not neighbours (then y_1[s] = y_1[t] = 0)
   if (threadIdx.x == 0 && !adjacent) {
-    const double vs = store(s, -a1 * q1s);
-    const double vt = store(t, -a1 * q1t);
+    const int32_t base = (row_ptr[s + 1] - row_ptr[s]) + (row_ptr[t + 1] - row_ptr[t]);
+    const double vs = store(s, -a1 * q1s, base);
+    const double vt = store(t, -a1 * q1t, base + 1);
     acc += ds * vs * vs + dt * vt * vt;
   }
   bb = block_sum(acc, sm);

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_first(const int32_t *__restrict__ row_p
   double a1, bb;
   first_iteration(
       row_ptr, col, w64, deg, s, t, c,
-      [&](int32_t u, double val) {
+      [&](int32_t u, double val, int32_t) {
         const VT x = (VT)val;
         U1[u] = x;
         return (double)x;

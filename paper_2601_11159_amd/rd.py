@@ -31,6 +31,7 @@ RD_PROFILE = 0x2
 RD_GENERAL_PATH = 0x4
 RD_REORDER = 0x8
 RD_NO_COMPACT = 0x10
+RD_NO_SPARSE2 = 0x20
 RD_F64 = 0
 RD_F32 = 1
 

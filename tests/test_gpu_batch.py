@@ -170,10 +170,18 @@ def test_autotuned_width_and_schedule(tmp_path, monkeypatch):
         run = LZ.lanczos_rd(g, int(s[p]), int(t[p]), tol=1e-10, A=A, d=d)
         assert abs(out["r"][p] - run.r) / run.r <= 1e-4
     # a new handle on the same graph reads the choice back from the cache file
-    assert cache.read_text().split()[-3:] == [str(width), str(wave), str(long_deg)]
+    fields = cache.read_text().split()
+    assert fields[-4:-1] == [str(width), str(wave), str(long_deg)]
+    assert float(fields[-1]) > 0.0  # product time per column (ms)
     G2 = rd.RDGraph(g.n, g.u, g.v)
     assert G2.tune_width(rd.RD_F32, len(s)) == width
     assert G2.batch_schedule() == (wave, long_deg)
+    # a line without the time (four fields) is still read
+    cache.write_text(" ".join(fields[:-1]) + "\n")
+    G3 = rd.RDGraph(g.n, g.u, g.v)
+    assert G3.tune_width(rd.RD_F32, len(s)) == width
+    out3 = G3.query_batch(s, t, 1e-4, _opts(precision=rd.RD_F32))
+    np.testing.assert_allclose(out3["r"], out["r"], rtol=2e-4)
 
 
 @pytest.mark.parametrize("ro", [1, 2])

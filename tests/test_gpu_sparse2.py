@@ -1,0 +1,138 @@
+"""GPU parity of the sparse second iteration of the batched path: pairs whose
+second product touches few adjacency entries compute it from the support of
+q_2 (a fixed-point scatter over N(S)) instead of a dense product over the
+block. The results must agree with the dense FP64 oracle, with the same run
+under RD_NO_SPARSE2 (dense second products) to rounding, and with themselves
+bit for bit from run to run."""
+
+import numpy as np
+import pytest
+
+from oracle import dense as D
+from paper_2601_11159_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2601_11159_amd import rd  # noqa: E402
+
+
+def _graphs():
+    return {
+        "grid": I.grid(30, 30),
+        "power_law": I.chung_lu(3000, 2.3, 8.0, seed=41),
+        "weighted": I.random_connected(800, extra=4000, seed=42, weighted=True),
+        "tree": I.random_tree(600, seed=43, weighted=True),
+        "star": I.star(300),
+    }
+
+
+GRAPHS = _graphs()
+
+
+def _pairs(g, count, seed):
+    s, t = I.uniform_pairs(g.n, count, seed)
+    s, t = s.copy(), t.copy()
+    # adjacent pairs, a pair at a degree-1 node and a repeated node
+    u, v = int(g.u[0]), int(g.v[0])
+    s[0], t[0] = u, v
+    s[1], t[1] = v, u
+    deg = np.bincount(np.concatenate([g.u, g.v]), minlength=g.n)
+    leaf = int(np.argmin(deg))
+    s[2] = leaf
+    if t[2] == leaf:
+        t[2] = (leaf + 1) % g.n
+    t[3] = s[3]
+    return s.astype(np.int32), t.astype(np.int32)
+
+
+def _run(G, s, t, tol, flags=0, **kw):
+    o = rd.rd_default_options(flags=rd.RD_GENERAL_PATH | flags, **kw)
+    return G.query_batch(s, t, tol, o)
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+@pytest.mark.parametrize("prec,tol,bar", [(rd.RD_F64, 1e-10, 1e-8), (rd.RD_F32, 1e-5, 2e-3)])
+def test_sparse2_against_oracle(name, prec, tol, bar):
+    g = GRAPHS[name]
+    s, t = _pairs(g, 150, seed=44)
+    mask = s != t
+    truth = np.zeros(len(s))
+    truth[mask] = D.rd_all(g, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    out = _run(G, s, t, tol, precision=prec, block_width=32)
+    assert np.all(out["status"] == rd.RD_OK)
+    assert out["r"][3] == 0.0 and out["iters"][3] == 0
+    err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+    assert err.max() <= bar, (name, err.max())
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+@pytest.mark.parametrize("k", [2, 3, 4, 9])
+def test_sparse2_matches_dense_second_product(name, k):
+    # the same number of iterations on both paths: r_hat_k agrees to rounding
+    g = GRAPHS[name]
+    s, t = _pairs(g, 100, seed=45)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    a = _run(G, s, t, 1e-6, fixed_k=k, block_width=32)
+    b = _run(G, s, t, 1e-6, rd.RD_NO_SPARSE2, fixed_k=k, block_width=32)
+    mask = s != t
+    # a Krylov space exhausted before k stops both runs early, at the same step
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    assert np.all(a["iters"][mask] <= k)
+    np.testing.assert_allclose(a["r"][mask], b["r"][mask], rtol=1e-11)
+
+
+def test_sparse2_is_taken_and_repeatable():
+    # on a 60x60 grid every pair's scatter (about 40 entries) is far below the
+    # cost cap (nnz * 4 / 256 = 221 entries in FP32 at an explicit width)
+    g = I.grid(60, 60)
+    s, t = I.uniform_pairs(g.n, 300, seed=46)
+    G = rd.RDGraph(g.n, g.u, g.v, reorder=True)
+    o = dict(precision=rd.RD_F32, fixed_k=3, block_width=64)
+    runs = [_run(G, s, t, 1e-6, **o) for _ in range(2)]
+    dense = _run(G, s, t, 1e-6, rd.RD_NO_SPARSE2, **o)
+    assert runs[0].tobytes() == runs[1].tobytes()
+    # in FP32 the dense second product rounds y_2 to FP32 and the sparse step
+    # does not, so the bits differ wherever the sparse step was taken
+    assert np.count_nonzero(runs[0]["r"] != dense["r"]) > len(s) // 2
+    np.testing.assert_allclose(runs[0]["r"], dense["r"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", [rd.RD_F64, rd.RD_F32])
+@pytest.mark.parametrize("width", [16, 64, 256])
+def test_sparse2_refill_and_compaction(prec, width):
+    # many more pairs than columns: refills at every iteration, then the tail
+    # narrows the block; hub pairs mix dense and sparse second iterations
+    g = GRAPHS["power_law"]
+    s1, t1 = I.uniform_pairs(g.n, 400, seed=47)
+    s2, t2 = I.hub_pairs(g, 200, seed=48)
+    s = np.concatenate([s1, s2]).astype(np.int32)
+    t = np.concatenate([t1, t2]).astype(np.int32)
+    mask = s != t
+    Lp = D.pinv(D.laplacian(g))
+    truth = np.zeros(len(s))
+    truth[mask] = D.rd_from_pinv(Lp, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v, reorder=True)
+    tol, bar = (1e-10, 1e-8) if prec == rd.RD_F64 else (1e-5, 2e-3)
+    out = _run(G, s, t, tol, precision=prec, block_width=width)
+    assert np.all(out["status"] == rd.RD_OK)
+    err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+    assert err.max() <= bar
+
+
+def test_sparse2_weighted_after_set_weights():
+    g = GRAPHS["weighted"]
+    s, t = _pairs(g, 80, seed=49)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    _run(G, s, t, 1e-10, block_width=16)
+    w2 = np.asarray(g.w, dtype=np.float64) * np.linspace(0.5, 2.0, g.m)
+    G.set_weights(w2)
+    g2 = I.Graph(g.n, g.u, g.v, w2, "reweighted")
+    mask = s != t
+    truth = D.rd_all(g2, s[mask], t[mask])
+    out = _run(G, s, t, 1e-10, block_width=16)
+    np.testing.assert_allclose(out["r"][mask], truth, rtol=1e-8)
