@@ -202,8 +202,9 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
  * The block width rd_query_batch uses when rd_options.block_width is 0, and
  * the row-bin schedule of its sparse product. First the width among 32, 64,
  * 128, 256 (not wider than needed for npairs) whose sparse product takes the
- * least time per column on this graph (a wider width only when it is at least
- * 5% faster per column than the narrower best); then, at that width, the schedule
+ * least time per column on this graph (the fastest of five products each; a
+ * wider width only when it is at least 2% faster per column than the narrower
+ * best); then, at that width, the schedule
  * (entries per wavefront work item: 128, 256 or 512; rows longer than 512,
  * 1024 or 2048 entries get a workgroup of their own) with the least time.
  * Measured on first use with HIP events on `stream` (NULL: the handle's

@@ -2113,9 +2113,9 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
                      g->deg, (const VT *)bw->X[1], (const VT *)bw->X[2], (VT *)bw->X[0], bw->ctrl,
                      bw->part, bw->ldp, bw->qstate + 3, (VT *)nullptr, (VT *)nullptr, 0,
                      (double *)nullptr, (VT *)nullptr);
-  hipEvent_t e0, e1;
-  RD_HIP(hipEventCreate(&e0));
-  RD_HIP(hipEventCreate(&e1));
+  constexpr int NT = 5;
+  hipEvent_t ev[NT + 1];
+  for (hipEvent_t &e : ev) RD_HIP(hipEventCreate(&e));
   auto once = [&]() {
     if (g->unit)
       launch_spmm<VT, B, false>(g, bw, (const VT *)bw->X[0], (const VT *)bw->X[2], (VT *)bw->X[1], st,
@@ -2125,15 +2125,21 @@ static float probe_spmm(rd_graph g, BatchWork *bw, hipStream_t st) {
                                bw->qstate + 3);
   };
   once();
-  RD_HIP(hipEventRecord(e0, st));
-  for (int k = 0; k < 3; ++k) once();
-  RD_HIP(hipEventRecord(e1, st));
-  RD_HIP(hipEventSynchronize(e1));
-  float ms = 0.f;
-  RD_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ms / 3.f;
+  RD_HIP(hipEventRecord(ev[0], st));
+  for (int k = 0; k < NT; ++k) {
+    once();
+    RD_HIP(hipEventRecord(ev[k + 1], st));
+  }
+  RD_HIP(hipEventSynchronize(ev[NT]));
+  // the fastest of the products: the least disturbed by other work on the chip
+  float best = 1e30f;
+  for (int k = 0; k < NT; ++k) {
+    float ms = 0.f;
+    RD_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+    best = std::min(best, ms);
+  }
+  for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+  return best;
 }
 
 template <typename VT>
@@ -2194,10 +2200,9 @@ static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npair
       for (int32_t B : {32, 64, 128, 256}) {
         if (B > 32 && B / 2 >= npairs) break;  // wider than the work: no gain
         const double per_col = probe(B) / B;
-        // a wider block must be clearly faster per column: it also refills
-        // more columns per iteration and leaves a longer tail (on a 4M-node
-        // power-law graph 256 probed within 5% of 64 but ran 5% slower)
-        if (per_col < best_t * 0.95) {
+        // a wider block must be faster per column by more than the probe's
+        // noise: it also leaves a longer tail of idle columns
+        if (per_col < best_t * 0.98) {
           best_t = per_col;
           best = B;
         }
