@@ -78,8 +78,9 @@ typedef enum {
                                (u, v), u in that support, adds w_uv w_1[u] / d_v to v's
                                sum in 64-bit fixed point (integer sums do not depend on the
                                order, so results stay the same from run to run), and the
-                               pair joins the dense iterations at the third. Results differ
-                               only by rounding. Not used by rd_grad_edges or refine. */
+                               pair joins the dense iterations at the third (with the
+                               potentials' second terms, for rd_grad_edges and refine, also
+                               written on that support). Results differ only by rounding. */
 
 /* weight / vector dtypes */
 #define RD_F64 0

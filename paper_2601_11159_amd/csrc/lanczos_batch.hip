@@ -951,6 +951,9 @@ struct S2Col {
   uint32_t pad;
   int32_t sexp;    // the sums are kept in units of 2^-sexp
   double alpha;    // alpha_2
+  double pa, xb;   // potentials: p_2 = q_2 + pa p_1, x_2 = x_1 + xb p_2
+  int32_t adv;     // alpha_2 advanced the run (the potentials take their second term)
+  int32_t pad2;
   unsigned long long bhi, blo;  // ||w_2||_D^2 in units of 2^-58 (two's complement) and 2^-90
 };
 
@@ -980,7 +983,7 @@ __global__ __launch_bounds__(256) void k_first_batch(
   __syncthreads();
   const int32_t s = S0.s, t = S0.t;
   const int32_t L = (row_ptr[s + 1] - row_ptr[s]) + (row_ptr[t + 1] - row_ptr[t]) + 2;
-  const bool lst = !GRAD && s2 && L <= lcap;
+  const bool lst = s2 && L <= lcap;
   int32_t *lu = Lu + (size_t)j * lcap;
   double *lw = Lw + (size_t)j * lcap;
   int64_t *lp = Lp + (size_t)j * (lcap + 1);
@@ -1245,8 +1248,14 @@ __global__ __launch_bounds__(256) void k_s2_alpha(int32_t n, S2Col *__restrict__
   a = block_sum(a, sm);
   if (threadIdx.x == 0) {
     LzState S = S0;
+    const double delta_prev = S.delta, beta_i = S.beta;
     scalar_after_alpha(S, a, nullptr, nullptr);
     s2c[j].alpha = a;
+    // coefficients of the potential recurrence for i = 2 (as in k_control)
+    const bool adv = S.k == 2;
+    s2c[j].adv = adv ? 1 : 0;
+    s2c[j].pa = adv ? beta_i / delta_prev : 0.0;
+    s2c[j].xb = adv ? S.omega / S.delta : 0.0;
     st[j] = S;
   }
 }
@@ -1332,19 +1341,26 @@ __global__ __launch_bounds__(256) void k_s2_write(
 
 // On S (block j: column j, fixed order): w_2 = y_2 - alpha_2 q_2 in place of the
 // y_2 that k_s2_write stored (S is inside N(S)), and the norm corrected by the
-// difference.
-template <typename VT, int B>
+// difference. GRAD: the potentials' second terms, which live on S too:
+// p_2 = q_2 + pa p_1 and x_2 = x_1 + xb p_2 (also when the run stopped at
+// alpha_2, as the dense update adds a stopped run's last term).
+template <typename VT, int B, bool GRAD>
 __global__ __launch_bounds__(256) void k_s2_fix(int32_t n, S2Col *__restrict__ s2c, int32_t lcap,
                                                 const int32_t *__restrict__ Lu, const double *__restrict__ Lw,
                                                 const double *__restrict__ deg, const LzState *__restrict__ st,
-                                                VT *__restrict__ W, const int32_t *__restrict__ active) {
+                                                VT *__restrict__ W, VT *__restrict__ P, VT *__restrict__ X,
+                                                const int32_t *__restrict__ active) {
   if (*active == 0) return;
   const int j = blockIdx.x;
-  if (s2c[j].E == 0 || st[j].status != LZ_RUNNING) return;
+  if (s2c[j].E == 0) return;
+  const bool running = st[j].status == LZ_RUNNING;
+  const bool pot = GRAD && s2c[j].adv;
+  if (!running && !pot) return;
   __shared__ double sm[256 / 64];
   const LzState &S = st[j];
   const int32_t L = s2c[j].L;
   const double alpha = s2c[j].alpha;
+  const double pa = s2c[j].pa, xb = s2c[j].xb;
   const double sig = S.sig_cur;
   const int32_t *lu = Lu + (size_t)j * lcap;
   const double *lw = Lw + (size_t)j * lcap;
@@ -1353,13 +1369,21 @@ __global__ __launch_bounds__(256) void k_s2_fix(int32_t n, S2Col *__restrict__ s
     const int32_t u = lu[k];
     if (u < 0) continue;
     const size_t ix = (size_t)u * B + j;
-    const double x0 = (double)W[ix];  // y_2[u] as k_s2_write stored it
-    const VT x = (VT)(x0 - alpha * (sig * lw[k]));
-    W[ix] = x;
-    d += deg[u] * ((double)x * (double)x - x0 * x0);
+    const double q2 = sig * lw[k];
+    if (running) {
+      const double x0 = (double)W[ix];  // y_2[u] as k_s2_write stored it
+      const VT x = (VT)(x0 - alpha * q2);
+      W[ix] = x;
+      d += deg[u] * ((double)x * (double)x - x0 * x0);
+    }
+    if (pot) {
+      const double p = q2 + pa * (double)P[ix];
+      P[ix] = (VT)p;
+      X[ix] = (VT)((double)X[ix] + xb * p);
+    }
   }
   d = block_sum(d, sm);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && running) {
     // the norm's two words take the signed correction: hi floor, lo >= 0
     const double th = d * S2_BETA_UNIT;
     const double fh = floor(th);
@@ -1748,7 +1772,7 @@ static void launch_spmm(rd_graph g, BatchWork *bw, const VT *Ucur, const VT *Upr
 template <typename VT, int B, bool GRAD>
 static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm, hipStream_t st) {
   const int32_t *active = bw->qstate + 1;
-  const bool s2 = !GRAD && prm.s2;
+  const bool s2 = prm.s2;
   hipLaunchKernelGGL((k_first_batch<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->row_ptr, g->col,
                      (const double *)g->w64, g->deg, W, bw->st, bw->ctrl, (VT *)bw->P, (VT *)bw->Xp,
                      active, s2 ? 1 : 0, prm.s2_ecap, bw->s2_lcap, bw->s2_lu, bw->s2_lw, bw->s2_lp, bw->s2c,
@@ -1775,9 +1799,9 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm,
                      bw->s2c, bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot,
                      (const int32_t *)bw->s2_lu, (const int64_t *)bw->s2_lp, g->row_ptr, g->col, g->deg,
                      bw->s2_acc, (const unsigned long long *)bw->s2_own, (const LzState *)bw->st, W, active);
-  hipLaunchKernelGGL((k_s2_fix<VT, B>), dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
+  hipLaunchKernelGGL((k_s2_fix<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
                      (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, (const LzState *)bw->st,
-                     W, active);
+                     W, (VT *)bw->P, (VT *)bw->Xp, active);
   hipLaunchKernelGGL(k_s2_beta, dim3(1), dim3(256), 0, st, B, bw->s2c, bw->st, bw->ctrl, active);
 }
 
@@ -1806,7 +1830,7 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
   else
     launch_spmm<VT, B, true>(g, bw, Ucur, Uprev, Y, st, active, prof);
   int32_t np = bw->grid_short + bw->nlong;
-  if (!GRAD && prm.s2) {
+  if (prm.s2) {
     hipLaunchKernelGGL((k_s2_prev<VT, B>), dim3(B), dim3(256), 0, st, (const S2Col *)bw->s2c, bw->s2_lcap,
                        (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, Ucur, Y, bw->ctrl,
                        bw->part, bw->ldp, np, active);
@@ -1958,7 +1982,7 @@ static int64_t batch_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int3
   // reductions around it) over the cost of one scatter entry, else
   // nnz * size / 256 entries (the two measured optima were nnz * 4 / 512 for
   // a power-law graph in FP32 and nnz * 8 / 128 for another in FP64)
-  prm.s2 = !GRAD && prm.s2 && prm.reorth == 0 && s2_reserve(g, bw, B, st);
+  prm.s2 = prm.s2 && prm.reorth == 0 && s2_reserve(g, bw, B, st);
   const int pi = sizeof(VT) == 8 ? RD_F64 : RD_F32;
   if (bw->tuned[pi] == B && bw->tuned_col_ms[pi] > 0.0)
     prm.s2_ecap = (int64_t)(bw->tuned_col_ms[pi] * 1.15 * 1e6 / S2_ENTRY_NS);
@@ -2293,6 +2317,7 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
     }
     if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
+    prm.s2 = !(opt.flags & RD_NO_SPARSE2);
     const bool prof = opt.flags & RD_PROFILE;
     if (opt.refine) {
       // groups of B pairs with potentials, r reported as the FP64 energy
@@ -2302,7 +2327,6 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
         grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
     } else {
       const bool compact = !(opt.flags & RD_NO_COMPACT);
-      prm.s2 = !(opt.flags & RD_NO_SPARSE2);
       if (opt.precision == RD_F64)
         batch_dispatch<double>(g, bw, B, npairs, ds, dt, prm, dout, st, prof, compact);
       else
@@ -2383,6 +2407,7 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
     RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
     RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
+    prm.s2 = !(opt.flags & RD_NO_SPARSE2);
     if (opt.precision == RD_F64)
       grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st, opt.flags & RD_PROFILE);
     else

@@ -136,3 +136,45 @@ def test_sparse2_weighted_after_set_weights():
     truth = D.rd_all(g2, s[mask], t[mask])
     out = _run(G, s, t, 1e-10, block_width=16)
     np.testing.assert_allclose(out["r"][mask], truth, rtol=1e-8)
+
+
+@pytest.mark.parametrize("prec,tol,rtol", [(rd.RD_F64, 1e-10, 1e-9), (rd.RD_F32, 1e-5, 2e-4)])
+def test_sparse2_gradient_and_refine(prec, tol, rtol):
+    # potentials take their second term from the sparse step: the edge
+    # gradient and the refined energy match the dense-second-product runs and
+    # the dense oracle
+    g = GRAPHS["weighted"]
+    s, t = _pairs(g, 120, seed=50)
+    s, t = s[s != t], t[s != t]
+    gbar = np.linspace(0.5, 1.5, len(s))
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    o = dict(precision=prec, block_width=32, flags=rd.RD_GENERAL_PATH)
+    fa, ga = G.grad_edges(s, t, gbar, tol, rd.rd_default_options(**o))
+    o2 = dict(o, flags=rd.RD_GENERAL_PATH | rd.RD_NO_SPARSE2)
+    fb, gb = G.grad_edges(s, t, gbar, tol, rd.rd_default_options(**o2))
+    if prec == rd.RD_F64:
+        np.testing.assert_array_equal(fa["iters"], fb["iters"])
+    assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) <= rtol
+    Lp = D.pinv(D.laplacian(g))
+    ref = D.grad_edges(g, Lp, s, t, gbar)
+    assert np.linalg.norm(ga - ref) / np.linalg.norm(ref) <= (1e-6 if prec == rd.RD_F64 else 2e-3)
+    ra = G.query_batch(s, t, tol, rd.rd_default_options(refine=1, **o))
+    rb = G.query_batch(s, t, tol, rd.rd_default_options(refine=1, **o2))
+    np.testing.assert_allclose(ra["r"], rb["r"], rtol=rtol)
+    np.testing.assert_allclose(ra["r"], D.rd_from_pinv(Lp, s, t), rtol=1e-8 if prec == rd.RD_F64 else 2e-4)
+
+
+def test_sparse2_gradient_stops_at_second_iteration():
+    # fixed_k = 2: the run stops at the sparse step; the potential keeps its
+    # second term, as on the dense path
+    g = GRAPHS["power_law"]
+    s, t = I.uniform_pairs(g.n, 70, seed=51)
+    s, t = s[s != t], t[s != t]
+    G = rd.RDGraph(g.n, g.u, g.v)
+    o = dict(block_width=16, fixed_k=2)
+    fa, ga = G.grad_edges(s, t, None, 1e-6, rd.rd_default_options(**o))
+    fb, gb = G.grad_edges(s, t, None, 1e-6, rd.rd_default_options(flags=rd.RD_NO_SPARSE2, **o))
+    assert np.all(fa["iters"] <= 2)
+    np.testing.assert_array_equal(fa["iters"], fb["iters"])
+    np.testing.assert_allclose(fa["r"], fb["r"], rtol=1e-11)
+    assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) <= 1e-9
