@@ -71,7 +71,7 @@ def test_sparse2_against_oracle(name, prec, tol, bar):
 
 
 @pytest.mark.parametrize("name", sorted(GRAPHS))
-@pytest.mark.parametrize("k", [2, 3, 4, 9])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 9])
 def test_sparse2_matches_dense_second_product(name, k):
     # the same number of iterations on both paths: r_hat_k agrees to rounding
     g = GRAPHS[name]
@@ -178,3 +178,29 @@ def test_sparse2_gradient_stops_at_second_iteration():
     np.testing.assert_array_equal(fa["iters"], fb["iters"])
     np.testing.assert_allclose(fa["r"], fb["r"], rtol=1e-11)
     assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) <= 1e-9
+
+
+def _double_star(leaves):
+    # centres 0 and 1 joined by an edge, each with `leaves` leaves: every edge
+    # is a bridge, so r adds up along the path (1 per edge)
+    n = 2 + 2 * leaves
+    u = np.concatenate([[0], np.zeros(leaves, np.int64), np.ones(leaves, np.int64)])
+    v = np.concatenate([[1], 2 + np.arange(leaves), 2 + leaves + np.arange(leaves)])
+    return I.Graph(n, u.astype(np.int32), v.astype(np.int32), None, f"double_star_{leaves}")
+
+
+@pytest.mark.parametrize("flags", [0, rd.RD_NO_SPARSE2])
+def test_sparse2_list_capacity_fallback(flags):
+    # deg(0) + deg(1) + 2 = 66,004 list slots exceed the 65,535 a column's list
+    # holds: the pair (0, 1) takes the dense second product, the others the
+    # sparse one or the dense one by cost; closed-form resistances
+    leaves = 33000
+    g = _double_star(leaves)
+    a, b = 2, 2 + leaves  # a leaf of each centre
+    s = np.array([0, a, a, 0, a, a + 1], np.int32)
+    t = np.array([1, b, 1, b, a + 1, 0], np.int32)
+    truth = np.array([1.0, 3.0, 2.0, 2.0, 2.0, 1.0])
+    G = rd.RDGraph(g.n, g.u, g.v)
+    out = _run(G, s, t, 1e-10, flags, block_width=16)
+    assert np.all(out["status"] == rd.RD_OK)
+    np.testing.assert_allclose(out["r"], truth, rtol=1e-9)
