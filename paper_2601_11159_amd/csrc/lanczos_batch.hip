@@ -948,7 +948,7 @@ struct S2Col {
   int64_t E;       // scatter entries of the current step (0: none)
   int32_t L;       // list slots of the column's current list (deg_s + deg_t + 2)
   int32_t nch;     // pieces: rows of the list cut into S2_PIECE entries
-  uint32_t pad;
+  uint32_t unused;
   int32_t sexp;    // the sums are kept in units of 2^-sexp
   double alpha;    // alpha_2
   double pa, xb;   // potentials: p_2 = q_2 + pa p_1, x_2 = x_1 + xb p_2
@@ -1345,7 +1345,7 @@ __global__ __launch_bounds__(256) void k_s2_write(
 // p_2 = q_2 + pa p_1 and x_2 = x_1 + xb p_2 (also when the run stopped at
 // alpha_2, as the dense update adds a stopped run's last term).
 template <typename VT, int B, bool GRAD>
-__global__ __launch_bounds__(256) void k_s2_fix(int32_t n, S2Col *__restrict__ s2c, int32_t lcap,
+__global__ __launch_bounds__(256) void k_s2_fix(S2Col *__restrict__ s2c, int32_t lcap,
                                                 const int32_t *__restrict__ Lu, const double *__restrict__ Lw,
                                                 const double *__restrict__ deg, const LzState *__restrict__ st,
                                                 VT *__restrict__ W, VT *__restrict__ P, VT *__restrict__ X,
@@ -1799,7 +1799,7 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm,
                      bw->s2c, bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot,
                      (const int32_t *)bw->s2_lu, (const int64_t *)bw->s2_lp, g->row_ptr, g->col, g->deg,
                      bw->s2_acc, (const unsigned long long *)bw->s2_own, (const LzState *)bw->st, W, active);
-  hipLaunchKernelGGL((k_s2_fix<VT, B, GRAD>), dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
+  hipLaunchKernelGGL((k_s2_fix<VT, B, GRAD>), dim3(B), dim3(256), 0, st, bw->s2c, bw->s2_lcap,
                      (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, (const LzState *)bw->st,
                      W, (VT *)bw->P, (VT *)bw->Xp, active);
   hipLaunchKernelGGL(k_s2_beta, dim3(1), dim3(256), 0, st, B, bw->s2c, bw->st, bw->ctrl, active);
@@ -2316,8 +2316,8 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
       return RD_OK;
     }
     if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
-    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
-    prm.s2 = !(opt.flags & RD_NO_SPARSE2);
+    RunParams prm{eps,       opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth,
+                  GRAD_NONE, nullptr,       (opt.flags & RD_NO_SPARSE2) ? 0 : 1, 0};
     const bool prof = opt.flags & RD_PROFILE;
     if (opt.refine) {
       // groups of B pairs with potentials, r reported as the FP64 energy
@@ -2406,8 +2406,8 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
     if (B == 0) B = autotune_width(g, bw, opt.precision, std::max(npairs, 1), st);
     RD_REQUIRE(B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
-    RunParams prm{eps, opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth};
-    prm.s2 = !(opt.flags & RD_NO_SPARSE2);
+    RunParams prm{eps,       opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth,
+                  GRAD_NONE, nullptr,       (opt.flags & RD_NO_SPARSE2) ? 0 : 1, 0};
     if (opt.precision == RD_F64)
       grad_dispatch<double>(g, bw, B, npairs, ds, dt, dg, prm, dout, dgw, st, opt.flags & RD_PROFILE);
     else
