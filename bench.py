@@ -281,6 +281,27 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
+def copy_bandwidth_gbs(torch, gib: int = 1, reps: int = 5) -> float:
+    """Achievable device bandwidth on this GPU: a torch device-to-device copy
+    of `gib` GiB (bytes read + bytes written per second), HIP events on the
+    current stream."""
+    n = gib * 256 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * gib * 2**30 / (ms * 1e-3) / 1e9
+
+
 def load_traffic(workload: str, width: int):
     """Measured HBM bytes per launch of k_spmm_short for this workload and
     width, from the committed counter summary, when the kernel source is
@@ -433,12 +454,19 @@ def main():
     wave, long_deg = G.batch_schedule()
     traffic = load_traffic(args.workload + ("/reordered" if args.reorder else "") + f"/w{wave}_l{long_deg}",
                            width) if width else None
+    copy_gbs = copy_bandwidth_gbs(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     roofline = {
         "kernel": "k_spmm_short (batched FP32 sparse product over the short rows)",
         "bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic, "avg_launch_ms": round(avg_ms, 4), "launches": k_launches,
         "alg_bytes_per_launch": k_bytes,
+        # achievable stream rate on this machine (1 GiB torch copy, read + write),
+        # and the rate of the measured bytes against the peak
+        "copy_gbs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4) if achieved else None,
+        "traffic_frac": round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
     }
     plain_avg_ms = pk_ms / max(pk_launches, 1)
     plain_roof = {
