@@ -1142,17 +1142,28 @@ __global__ __launch_bounds__(256) void k_first_batch(
     for (int64_t r = lp[k]; r < lp[k + 1]; ++r) ps[r] = k;
 }
 
-// Piece offsets of the columns taking the sparse step: cpre[j] = sum of nch
-// over the columns before j (one thread, B <= 256).
-__global__ void k_s2_plan(int32_t B, const S2Col *__restrict__ s2c, int32_t *__restrict__ cpre,
-                          const int32_t *__restrict__ active) {
-  if (*active == 0 || threadIdx.x != 0) return;
-  int32_t acc = 0;
-  for (int c = 0; c < B; ++c) {
-    cpre[c] = acc;
-    if (s2c[c].E > 0) acc += s2c[c].nch;
+// Piece offsets of the columns taking the sparse step, computed by every
+// workgroup into LDS: cp[j] = sum of nch over the columns before j, cp[B] the
+// total (B <= 256, a block of 256 threads).
+__device__ __forceinline__ void s2_offsets(int32_t B, const S2Col *__restrict__ s2c, int32_t *cp) {
+  __shared__ int32_t wtot[256 / 64];
+  const int j = threadIdx.x, lane = j & 63, wid = j >> 6;
+  const int32_t d = (j < B && s2c[j].E > 0) ? s2c[j].nch : 0;
+  int32_t x = d;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  cpre[B] = acc;
+  if (lane == 63) wtot[wid] = x;
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+  for (int w = 0; w < 256 / 64; ++w) {
+    if (w < wid) before += wtot[w];
+    tot += wtot[w];
+  }
+  if (j < B) cp[j] = before + x - d;
+  if (j == 0) cp[B] = tot;
+  __syncthreads();
 }
 
 // Column of piece c (the last j with cpre[j] <= c; cpre[0] = 0 <= c < cpre[B]).
@@ -1202,7 +1213,7 @@ __device__ __forceinline__ bool s2_count_is_zero(unsigned long long a) {
 // add found the count at zero: one entry per node.
 template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_s2_scatter(
-    int32_t B, int32_t n, const int32_t *__restrict__ cpre, const S2Col *__restrict__ s2c, int32_t lcap,
+    int32_t B, int32_t n, const S2Col *__restrict__ s2c, int32_t lcap,
     int64_t pcap, const int32_t *__restrict__ pslot, const int32_t *__restrict__ Lu,
     const double *__restrict__ Lw, const int64_t *__restrict__ Lp, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const double *__restrict__ w64, const double *__restrict__ deg,
@@ -1211,8 +1222,7 @@ __global__ __launch_bounds__(256) void k_s2_scatter(
   if (*active == 0) return;
   constexpr int NI = S2_PIECE / 64;
   __shared__ int32_t cp[257];
-  for (int i = threadIdx.x; i <= B; i += blockDim.x) cp[i] = cpre[i];
-  __syncthreads();
+  s2_offsets(B, s2c, cp);
   const int32_t total = cp[B];
   const int lane = threadIdx.x & 63;
   const int32_t nwv = gridDim.x * (256 / 64);
@@ -1298,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_s2_alpha(int32_t n, S2Col *__restrict__
 // that stopped at alpha_2 only clears).
 template <typename VT, int B>
 __global__ __launch_bounds__(256) void k_s2_write(
-    int32_t n, const int32_t *__restrict__ cpre, S2Col *__restrict__ s2c, int32_t lcap, int64_t pcap,
+    int32_t n, S2Col *__restrict__ s2c, int32_t lcap, int64_t pcap,
     const int32_t *__restrict__ pslot, const int32_t *__restrict__ Lu, const int64_t *__restrict__ Lp,
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ deg,
     unsigned long long *__restrict__ acc, const unsigned long long *__restrict__ own,
@@ -1306,8 +1316,7 @@ __global__ __launch_bounds__(256) void k_s2_write(
   if (*active == 0) return;
   constexpr int NI = S2_PIECE / 64;
   __shared__ int32_t cp[257];
-  for (int i = threadIdx.x; i <= B; i += blockDim.x) cp[i] = cpre[i];
-  __syncthreads();
+  s2_offsets(B, s2c, cp);
   const int32_t total = cp[B];
   const int lane = threadIdx.x & 63;
   const int32_t nwv = gridDim.x * (256 / 64);
@@ -1593,7 +1602,6 @@ struct BatchWork {
   int32_t *s2_pslot = nullptr;           // list slot of every piece: [s2_slots][s2_pcap]
   int64_t s2_pcap = 0;                   // row pieces per column at most
   S2Col *s2c = nullptr;                  // [256]
-  int32_t *s2_cpre = nullptr;            // [257]
   // autotune cache: chosen width and schedule per precision
   int32_t tuned[2] = {0, 0};
   int32_t tuned_wave[2] = {0, 0}, tuned_long[2] = {0, 0};
@@ -1627,7 +1635,6 @@ void batch_free(rd_graph g) {
   dev_free(bw->s2_lw);
   dev_free(bw->s2_lp);
   dev_free(bw->s2c);
-  dev_free(bw->s2_cpre);
   if (bw->qstate_host) (void)hipHostFree(bw->qstate_host);
   delete bw;
   g->batch = nullptr;
@@ -1701,7 +1708,6 @@ static BatchWork *batch_get(rd_graph g) {
   bw->cmap = (int32_t *)dev_alloc(128 * sizeof(int32_t));
   bw->s2c = (S2Col *)dev_alloc(256 * sizeof(S2Col));
   RD_HIP(hipMemset(bw->s2c, 0, 256 * sizeof(S2Col)));
-  bw->s2_cpre = (int32_t *)dev_alloc(257 * sizeof(int32_t));
   RD_HIP(hipHostMalloc((void **)&bw->qstate_host, 4 * sizeof(int32_t), hipHostMallocDefault));
   return bw;
 }
@@ -1812,24 +1818,23 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm,
                      bw->s2_pslot, bw->s2_pcap);
   if (!s2) return;
   const int32_t grid = 2048;  // 8192 wavefronts over the row pieces
-  hipLaunchKernelGGL(k_s2_plan, dim3(1), dim3(64), 0, st, B, (const S2Col *)bw->s2c, bw->s2_cpre, active);
   if (g->unit)
     hipLaunchKernelGGL(k_s2_scatter<false>, dim3(grid), dim3(256), 0, st, B, g->n,
-                       (const int32_t *)bw->s2_cpre, (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
+                       (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
                        (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw,
                        (const int64_t *)bw->s2_lp,
                        g->row_ptr, g->col, (const double *)nullptr, g->deg, bw->s2_acc, bw->s2_own, active);
   else
     hipLaunchKernelGGL(k_s2_scatter<true>, dim3(grid), dim3(256), 0, st, B, g->n,
-                       (const int32_t *)bw->s2_cpre, (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
+                       (const S2Col *)bw->s2c, bw->s2_lcap, bw->s2_pcap,
                        (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw,
                        (const int64_t *)bw->s2_lp,
                        g->row_ptr, g->col, (const double *)g->w64, g->deg, bw->s2_acc, bw->s2_own, active);
   hipLaunchKernelGGL(k_s2_alpha, dim3(B), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
                      (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg,
                      (const unsigned long long *)bw->s2_acc, bw->st, active);
-  hipLaunchKernelGGL((k_s2_write<VT, B>), dim3(grid), dim3(256), 0, st, g->n, (const int32_t *)bw->s2_cpre,
-                     bw->s2c, bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot,
+  hipLaunchKernelGGL((k_s2_write<VT, B>), dim3(grid), dim3(256), 0, st, g->n, bw->s2c, bw->s2_lcap,
+                     bw->s2_pcap, (const int32_t *)bw->s2_pslot,
                      (const int32_t *)bw->s2_lu, (const int64_t *)bw->s2_lp, g->row_ptr, g->col, g->deg,
                      bw->s2_acc, (const unsigned long long *)bw->s2_own, (const LzState *)bw->st, W, active);
   hipLaunchKernelGGL((k_s2_fix<VT, B, GRAD>), dim3(B), dim3(256), 0, st, bw->s2c, bw->s2_lcap,
