@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 def test_header_constants_match_binding():
     txt = open(os.path.join(ROOT, "include", "rd.h")).read()
     defs = dict(re.findall(r"#define (RD_[A-Z0-9_]+) (0x[0-9a-f]+|\d+)u?", txt))
-    assert set(defs) >= {"RD_DEVICE_PTRS", "RD_PROFILE", "RD_GENERAL_PATH", "RD_REORDER", "RD_F64", "RD_F32"}
+    assert set(defs) >= {"RD_DEVICE_PTRS", "RD_PROFILE", "RD_GENERAL_PATH", "RD_REORDER", "RD_NO_COMPACT",
+                         "RD_NO_SPARSE2", "RD_F64", "RD_F32"}
     for name, val in defs.items():
         assert getattr(rd, name) == int(val, 0), name
 
