@@ -190,11 +190,16 @@ rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
  * s == t get r = 0 without a slot). s, t are int32[npairs] and out
  * rd_result[npairs]; all three are device pointers when o->flags has
  * RD_DEVICE_PTRS. Options: precision, block_width (0: autotuned), reorth,
- * refine, and the flags RD_NO_COMPACT, RD_GENERAL_PATH, RD_PROFILE. Each
- * result is that of the same run done alone, up to rounding. Returns RD_E_ARG
- * for an id outside [0, n) (checked on the device), an unsupported
- * block_width or eps <= 0 without fixed_k; per-pair outcomes are in
- * out[p].status as for rd_query.
+ * refine, and the flags RD_NO_COMPACT, RD_NO_SPARSE2, RD_GENERAL_PATH,
+ * RD_PROFILE. Each result is that of the same run done alone, up to rounding,
+ * and the same from call to call bit for bit. Returns RD_E_ARG for an id
+ * outside [0, n) (checked on the device), an unsupported block_width or
+ * eps <= 0 without fixed_k; per-pair outcomes are in out[p].status as for
+ * rd_query. Device memory kept on the handle for later calls: three n x width
+ * vector blocks (RD_E_OOM when they do not fit), and for the sparse second
+ * iteration 8 bytes per node and column plus lists of 2 * max_degree + 2
+ * entries per column (when these would pass 24 GB or do not fit, the call
+ * takes dense second iterations instead).
  */
 rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
                          double eps, const rd_options *o, rd_result *out);

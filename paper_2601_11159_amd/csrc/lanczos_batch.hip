@@ -1714,7 +1714,7 @@ static BatchWork *batch_get(rd_graph g) {
 
 // Buffers of the sparse second iterations for B columns. Returns false (the
 // run then uses dense second iterations) when the per-node arrays would take
-// more than S2_MAX_BYTES.
+// more than S2_MAX_BYTES or device memory runs out.
 constexpr size_t S2_MAX_BYTES = (size_t)24 << 30;
 static bool s2_reserve(rd_graph g, BatchWork *bw, int32_t B, hipStream_t st) {
   if (B <= bw->s2_slots) return true;
@@ -1734,16 +1734,27 @@ static bool s2_reserve(rd_graph g, BatchWork *bw, int32_t B, hipStream_t st) {
   bw->s2_lp = nullptr;
   bw->s2_slots = 0;
   const int32_t lcap = (int32_t)std::min<int64_t>(2 * (int64_t)g->max_deg + 2, S2_LCAP_MAX);
-  bw->s2_acc = (unsigned long long *)dev_alloc((size_t)B * g->n * sizeof(unsigned long long));
-  bw->s2_lu = (int32_t *)dev_alloc((size_t)B * lcap * sizeof(int32_t));
-  bw->s2_lw = (double *)dev_alloc((size_t)B * lcap * sizeof(double));
-  bw->s2_lp = (int64_t *)dev_alloc((size_t)B * (lcap + 1) * sizeof(int64_t));
   // a column's pieces: at most one per list slot plus entries / S2_PIECE, and
   // at most s2_ecap <= nnz * 8 / 128 entries
-  bw->s2_pcap = lcap + g->nnz * 8 / 128 / S2_PIECE + 1;
-  bw->s2_own = (unsigned long long *)dev_alloc((size_t)B * bw->s2_pcap * (S2_PIECE / 64) *
-                                               sizeof(unsigned long long));
-  bw->s2_pslot = (int32_t *)dev_alloc((size_t)B * bw->s2_pcap * sizeof(int32_t));
+  const int64_t pcap = lcap + g->nnz * 8 / 128 / S2_PIECE + 1;
+  try {
+    bw->s2_acc = (unsigned long long *)dev_alloc((size_t)B * g->n * sizeof(unsigned long long));
+    bw->s2_lu = (int32_t *)dev_alloc((size_t)B * lcap * sizeof(int32_t));
+    bw->s2_lw = (double *)dev_alloc((size_t)B * lcap * sizeof(double));
+    bw->s2_lp = (int64_t *)dev_alloc((size_t)B * (lcap + 1) * sizeof(int64_t));
+    bw->s2_own = (unsigned long long *)dev_alloc((size_t)B * pcap * (S2_PIECE / 64) * sizeof(unsigned long long));
+    bw->s2_pslot = (int32_t *)dev_alloc((size_t)B * pcap * sizeof(int32_t));
+  } catch (const RdError &e) {
+    if (e.code != RD_E_OOM) throw;
+    // not enough device memory: this run takes dense second iterations
+    for (void **x : {(void **)&bw->s2_acc, (void **)&bw->s2_lu, (void **)&bw->s2_lw, (void **)&bw->s2_lp,
+                     (void **)&bw->s2_own, (void **)&bw->s2_pslot}) {
+      dev_free(*x);
+      *x = nullptr;
+    }
+    return false;
+  }
+  bw->s2_pcap = pcap;
   RD_HIP(hipMemsetAsync(bw->s2_acc, 0, (size_t)B * g->n * sizeof(unsigned long long), st));
   RD_HIP(hipMemsetAsync(bw->s2c, 0, 256 * sizeof(S2Col), st));
   bw->s2_lcap = lcap;
