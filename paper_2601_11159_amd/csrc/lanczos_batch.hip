@@ -981,12 +981,10 @@ struct S2Col {
   int64_t E;       // scatter entries of the current step (0: none)
   int32_t L;       // list slots of the column's current list (deg_s + deg_t + 2)
   int32_t nch;     // pieces: rows of the list cut into S2_PIECE entries
-  uint32_t unused;
   int32_t sexp;    // the sums are kept in units of 2^-sexp
+  int32_t adv;     // alpha_2 advanced the run (the potentials take their second term)
   double alpha;    // alpha_2
   double pa, xb;   // potentials: p_2 = q_2 + pa p_1, x_2 = x_1 + xb p_2
-  int32_t adv;     // alpha_2 advanced the run (the potentials take their second term)
-  int32_t pad2;
   unsigned long long bhi, blo;  // ||w_2||_D^2 in units of 2^-58 (two's complement) and 2^-90
 };
 
