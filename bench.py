@@ -503,9 +503,13 @@ def main():
                    "block_width": width, "block_width_source": "fixed" if args.width else "autotuned",
                    "row_schedule": dict(zip(("wave_nnz", "long_deg"), G.batch_schedule())),
                    "node_order": "decreasing degree (RD_REORDER)" if args.reorder else "as generated",
+                   "first_iterations": "iteration 1 from the rows of s and t; iteration 2 from the "
+                                       "support of q_2 where that scatter costs less than a dense column "
+                                       "(RD_NO_SPARSE2 off)",
                    "mean_iters": round(float(iters.mean()), 3)},
         "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,
-                       "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof},
+                       "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof,
+                       "first_iterations": "iteration 1 from the rows of s and t; dense from iteration 2"},
         "speedup_batched_vs_plain_fp64": round(value / plain_value, 2),
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
     }
