@@ -204,3 +204,34 @@ def test_sparse2_list_capacity_fallback(flags):
     out = _run(G, s, t, 1e-10, flags, block_width=16)
     assert np.all(out["status"] == rd.RD_OK)
     np.testing.assert_allclose(out["r"], truth, rtol=1e-9)
+
+
+def test_sparse2_handle_reused_across_widths():
+    # the sparse-step buffers grow with the width (16 -> 256) and are reused
+    # (-> 64); every run agrees with the dense oracle
+    g = GRAPHS["power_law"]
+    s, t = I.uniform_pairs(g.n, 200, seed=52)
+    mask = s != t
+    truth = np.zeros(len(s))
+    truth[mask] = D.rd_all(g, s[mask], t[mask])
+    G = rd.RDGraph(g.n, g.u, g.v, reorder=True)
+    for width in (16, 256, 64, 16):
+        out = _run(G, s, t, 1e-10, block_width=width)
+        assert np.all(out["status"] == rd.RD_OK)
+        err = np.abs(out["r"][mask] - truth[mask]) / truth[mask]
+        assert err.max() <= 1e-8, (width, err.max())
+
+
+def test_sparse2_iteration_cap_at_the_sparse_step():
+    # max_iters = 2: runs that need more stop as not converged right after the
+    # sparse step, with the same r_hat_2 and status as the dense path
+    g = GRAPHS["grid"]
+    s, t = _pairs(g, 60, seed=53)
+    G = rd.RDGraph(g.n, g.u, g.v)
+    a = _run(G, s, t, 1e-12, block_width=16, max_iters=2)
+    b = _run(G, s, t, 1e-12, rd.RD_NO_SPARSE2, block_width=16, max_iters=2)
+    np.testing.assert_array_equal(a["status"], b["status"])
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    assert np.any(a["status"] == rd.RD_E_NOT_CONVERGED)
+    mask = s != t
+    np.testing.assert_allclose(a["r"][mask], b["r"][mask], rtol=1e-11)
