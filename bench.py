@@ -509,7 +509,8 @@ def main():
                    "mean_iters": round(float(iters.mean()), 3)},
         "plain_fp64": {"value": round(plain_value, 2), "unit": "queries/s", "pairs_timed": npl,
                        "mean_iters": round(float(plain_it.mean()), 3), "roofline": plain_roof,
-                       "first_iterations": "iteration 1 from the rows of s and t; dense from iteration 2"},
+                       "first_iterations": "iteration 1 from the rows of s and t; iteration 2 from the "
+                                           "support of q_2 where that scatter has at most nnz/64 entries"},
         "speedup_batched_vs_plain_fp64": round(value / plain_value, 2),
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
     }

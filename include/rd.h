@@ -70,8 +70,10 @@ typedef enum {
                                the width (repeatedly, down to 16), so a tail of slow pairs does
                                not pay for idle columns. Results differ only by rounding. */
 
-#define RD_NO_SPARSE2 0x20u /* rd_options.flags: rd_query_batch runs the second Lanczos
-                               iteration of every pair as a dense product over the block.
+#define RD_NO_SPARSE2 0x20u /* rd_options.flags: rd_query and rd_query_batch run the second
+                               Lanczos iteration of every pair as a dense product (rd_query
+                               takes the sparse step below when the scatter has at most
+                               nnz/64 entries, and not for rd_query_trace).
                                By default (precision either, reorth 0), a pair whose second
                                product touches few adjacency entries computes it from the
                                support of q_2 alone, N(s) u N(t) u {s, t}: each entry

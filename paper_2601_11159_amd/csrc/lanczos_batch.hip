@@ -988,6 +988,83 @@ struct S2Col {
   unsigned long long bhi, blo;  // ||w_2||_D^2 in units of 2^-58 (two's complement) and 2^-90
 };
 
+// The rest of a column's list once its slots hold (node, stored w_1) or a
+// hole (node -1), for all 256 threads of a block: exclusive prefix sums of the
+// rows' piece counts into lp, the number of scatter entries, the fixed-point
+// unit from max |w_1| (mx: each thread's part), and, when the scatter has at
+// most s2_ecap entries, the column's record *sc and the slot of every piece.
+__device__ void s2_finish_list(const int32_t *__restrict__ row_ptr, int32_t L, const int32_t *__restrict__ lu,
+                               int64_t *__restrict__ lp, double mx, int64_t s2_ecap, S2Col *__restrict__ sc,
+                               int32_t *__restrict__ ps) {
+  __shared__ int64_t wsum[256 / 64];
+  __shared__ double wmax[256 / 64];
+  __shared__ int32_t go;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t carry = 0, ent = 0;
+  for (int32_t base = 0; base < L; base += 256) {
+    const int32_t k = base + threadIdx.x;
+    int64_t d = 0;
+    if (k < L) {
+      const int32_t u = lu[k];
+      if (u >= 0) {
+        const int32_t len = row_ptr[u + 1] - row_ptr[u];
+        d = (len + S2_PIECE - 1) / S2_PIECE;
+        ent += len;
+      }
+    }
+    int64_t x = d;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int64_t before = carry, tot = 0;
+    for (int w = 0; w < 256 / 64; ++w) {
+      if (w < wid) before += wsum[w];
+      tot += wsum[w];
+    }
+    if (k < L) lp[k] = before + x - d;
+    __syncthreads();
+    carry += tot;
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  ent = wave_sum(ent);
+  if (lane == 0) {
+    wmax[wid] = mx;
+    wsum[wid] = ent;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lp[L] = carry;
+    ent = 0;
+    for (int w = 0; w < 256 / 64; ++w) {
+      mx = fmax(mx, wmax[w]);
+      ent += wsum[w];
+    }
+    S2Col c = *sc;
+    c.L = L;
+    c.E = 0;
+    // (at most 2^22 pieces per column keeps the piece offsets of 256 columns in int32)
+    if (ent > 0 && ent <= s2_ecap && carry <= (1 << 22) && mx > 0.0) {
+      // |sum_u w_uv w_1[u] / d_v| <= max |w_1| < 2^e: units of 2^(e - 46) keep
+      // every sum below 2^46, which leaves 16 bits of the word for the count
+      int e;
+      (void)frexp(mx, &e);
+      c.E = ent;
+      c.nch = (int32_t)carry;
+      c.sexp = 46 - e;
+      c.bhi = c.blo = 0;
+    }
+    *sc = c;
+    go = c.E > 0;
+  }
+  __syncthreads();
+  if (!go) return;
+  for (int32_t k = threadIdx.x; k < L; k += blockDim.x)
+    for (int64_t r = lp[k]; r < lp[k + 1]; ++r) ps[r] = k;
+}
+
 // First iteration of every refilled column from the adjacency rows of s and t
 // (block j: column j). Writes w_1 into column j of W (zeroed by k_update),
 // completes iteration 1 of the column's scalars, and arms the next product to
@@ -1007,7 +1084,6 @@ __global__ __launch_bounds__(256) void k_first_batch(
   const int j = blockIdx.x;
   if (!starts_pair(ctrl[j].mode)) return;
   __shared__ double sm[256 / 64 + 2];
-  __shared__ int64_t wsum[256 / 64];
   __shared__ LzState S0;
   __shared__ int32_t take;
   if (threadIdx.x == 0) S0 = st[j];
@@ -1069,75 +1145,7 @@ __global__ __launch_bounds__(256) void k_first_batch(
   }
   __syncthreads();
   if (!take) return;
-  // exclusive prefix sums of the piece counts of the list's rows (empty
-  // slots: 0), and the number of scatter entries
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int64_t carry = 0, ent = 0;
-  for (int32_t base = 0; base < L; base += 256) {
-    const int32_t k = base + threadIdx.x;
-    int64_t d = 0;
-    if (k < L) {
-      const int32_t u = lu[k];
-      if (u >= 0) {
-        const int32_t len = row_ptr[u + 1] - row_ptr[u];
-        d = (len + S2_PIECE - 1) / S2_PIECE;
-        ent += len;
-      }
-    }
-    int64_t x = d;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int64_t y = __shfl_up(x, off, 64);
-      if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    int64_t before = carry, tot = 0;
-    for (int w = 0; w < 256 / 64; ++w) {
-      if (w < wid) before += wsum[w];
-      tot += wsum[w];
-    }
-    if (k < L) lp[k] = before + x - d;
-    __syncthreads();
-    carry += tot;
-  }
-  // the largest |w_1| sets the fixed-point unit
-  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  ent = wave_sum(ent);
-  if (lane == 0) {
-    sm[wid] = mx;
-    wsum[wid] = ent;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    lp[L] = carry;
-    ent = 0;
-    for (int w = 0; w < 256 / 64; ++w) {
-      mx = fmax(mx, sm[w]);
-      ent += wsum[w];
-    }
-    S2Col c = s2c[j];
-    c.L = L;
-    c.E = 0;
-    // (at most 2^22 pieces per column keeps the piece offsets of 256 columns in int32)
-    if (ent > 0 && ent <= s2_ecap && carry <= (1 << 22) && mx > 0.0) {
-      // |sum_u w_uv w_1[u] / d_v| <= max |w_1| < 2^e: units of 2^(e - 46) keep
-      // every sum below 2^46, which leaves 16 bits of the word for the count
-      int e;
-      (void)frexp(mx, &e);
-      c.E = ent;
-      c.nch = (int32_t)carry;
-      c.sexp = 46 - e;
-      c.bhi = c.blo = 0;
-    }
-    s2c[j] = c;
-    take = c.E > 0;
-  }
-  __syncthreads();
-  if (!take) return;
-  // the list slot of every piece
-  int32_t *ps = pslot + (size_t)j * pcap;
-  for (int32_t k = threadIdx.x; k < L; k += blockDim.x)
-    for (int64_t r = lp[k]; r < lp[k + 1]; ++r) ps[r] = k;
+  s2_finish_list(row_ptr, L, lu, lp, mx, s2_ecap, s2c + j, pslot + (size_t)j * pcap);
 }
 
 // Piece offsets of the columns taking the sparse step, computed by every
@@ -1502,6 +1510,47 @@ __global__ __launch_bounds__(256) void k_s2_prev(const S2Col *__restrict__ s2c, 
   }
 }
 
+// The list of S for a single-pair run, built from w_1 as its first iteration
+// stored it (U1, zero off S) with the slots k_first_batch uses, then finished
+// as there (slot 0 of the column arrays). No list when the run stopped or
+// the list would not fit.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_s2_list_single(const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col, const VT *__restrict__ U1,
+                                                        const LzState *__restrict__ st, int64_t s2_ecap,
+                                                        int32_t lcap, int32_t *__restrict__ Lu,
+                                                        double *__restrict__ Lw, int64_t *__restrict__ Lp,
+                                                        S2Col *__restrict__ s2c, int32_t *__restrict__ pslot) {
+  const int32_t s = st->s, t = st->t;
+  const int32_t rs = row_ptr[s], ds = row_ptr[s + 1] - rs;
+  const int32_t rt = row_ptr[t], dt = row_ptr[t + 1] - rt;
+  const int32_t L = ds + dt + 2;
+  if (st->status != LZ_RUNNING || L > lcap) {
+    if (threadIdx.x == 0) s2c->E = 0;
+    return;
+  }
+  for (int32_t k = threadIdx.x; k < L; k += blockDim.x) Lu[k] = -1;
+  __syncthreads();
+  double mx = 0.0;
+  auto put = [&](int32_t pos, int32_t u) {
+    const double x = (double)U1[u];
+    Lu[pos] = u;
+    Lw[pos] = x;
+    mx = fmax(mx, fabs(x));
+  };
+  for (int32_t p = threadIdx.x; p < ds; p += blockDim.x) put(p, col[rs + p]);
+  for (int32_t p = threadIdx.x; p < dt; p += blockDim.x) {
+    const int32_t u = col[rt + p];
+    if (row_find(row_ptr, col, s, u) < 0) put(ds + p, u);
+  }
+  if (threadIdx.x == 0 && row_find(row_ptr, col, s, t) < 0) {
+    put(L - 2, s);
+    put(L - 1, t);
+  }
+  __syncthreads();
+  s2_finish_list(row_ptr, L, Lu, Lp, mx, s2_ecap, s2c, pslot);
+}
+
 __global__ void k_batch_reset(int32_t B, LzState *__restrict__ st, ColCtrl *__restrict__ ctrl,
                               int32_t *__restrict__ qstate, S2Col *__restrict__ s2c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1702,6 +1751,11 @@ static BatchWork *batch_get(rd_graph g) {
   bw->ctrl = (ColCtrl *)dev_alloc(256 * sizeof(ColCtrl));
   bw->colsum = (double *)dev_alloc(256 * sizeof(double));
   bw->qstate = (int32_t *)dev_alloc(8 * sizeof(int32_t));
+  {
+    // [3] is the constant 1 that gates launches outside a batched run
+    const int32_t q0[8] = {0, 0, 0, 1, 0, 0, 0, 0};
+    RD_HIP(hipMemcpy(bw->qstate, q0, sizeof(q0), hipMemcpyHostToDevice));
+  }
   bw->flag = (int32_t *)dev_alloc(sizeof(int32_t));
   bw->cmap = (int32_t *)dev_alloc(128 * sizeof(int32_t));
   bw->s2c = (S2Col *)dev_alloc(256 * sizeof(S2Col));
@@ -1850,6 +1904,58 @@ static void launch_first(rd_graph g, BatchWork *bw, VT *W, const RunParams &prm,
                      (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, (const LzState *)bw->st,
                      W, (VT *)bw->P, (VT *)bw->Xp, active);
   hipLaunchKernelGGL(k_s2_beta, dim3(1), dim3(256), 0, st, B, bw->s2c, bw->st, bw->ctrl, active);
+}
+
+// The sparse second iteration of a single-pair run, one column of the batched
+// machinery: U1 holds w_1 (zero off S), U2 (zero) receives w_2, st is the
+// run's state after iteration 1. Enqueued on the stream; the step was taken
+// when the state then shows k = 2.
+template <typename VT>
+static void single_second_t(rd_graph g, BatchWork *bw, const VT *U1, VT *U2, LzState *st, int64_t ecap,
+                            hipStream_t stream) {
+  const int32_t *one = bw->qstate + 3;
+  const int32_t grid = 256;
+  hipLaunchKernelGGL(k_s2_list_single<VT>, dim3(1), dim3(256), 0, stream, g->row_ptr, g->col, U1,
+                     (const LzState *)st, ecap, bw->s2_lcap, bw->s2_lu, bw->s2_lw, bw->s2_lp, bw->s2c,
+                     bw->s2_pslot);
+  if (g->unit)
+    hipLaunchKernelGGL(k_s2_scatter<false>, dim3(grid), dim3(256), 0, stream, 1, g->n, (const S2Col *)bw->s2c,
+                       bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu,
+                       (const double *)bw->s2_lw, (const int64_t *)bw->s2_lp, g->row_ptr, g->col,
+                       (const double *)nullptr, g->deg, bw->s2_acc, bw->s2_own, one);
+  else
+    hipLaunchKernelGGL(k_s2_scatter<true>, dim3(grid), dim3(256), 0, stream, 1, g->n, (const S2Col *)bw->s2c,
+                       bw->s2_lcap, bw->s2_pcap, (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu,
+                       (const double *)bw->s2_lw, (const int64_t *)bw->s2_lp, g->row_ptr, g->col,
+                       (const double *)g->w64, g->deg, bw->s2_acc, bw->s2_own, one);
+  hipLaunchKernelGGL(k_s2_alpha, dim3(1), dim3(256), 0, stream, g->n, bw->s2c, bw->s2_lcap,
+                     (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg,
+                     (const unsigned long long *)bw->s2_acc, st, one);
+  hipLaunchKernelGGL((k_s2_write<VT, 1>), dim3(grid), dim3(256), 0, stream, g->n, bw->s2c, bw->s2_lcap,
+                     bw->s2_pcap, (const int32_t *)bw->s2_pslot, (const int32_t *)bw->s2_lu,
+                     (const int64_t *)bw->s2_lp, g->row_ptr, g->col, g->deg, bw->s2_acc,
+                     (const unsigned long long *)bw->s2_own, (const LzState *)st, U2, one);
+  hipLaunchKernelGGL((k_s2_fix<VT, 1, false>), dim3(1), dim3(256), 0, stream, bw->s2c, bw->s2_lcap,
+                     (const int32_t *)bw->s2_lu, (const double *)bw->s2_lw, g->deg, (const LzState *)st, U2,
+                     (VT *)nullptr, (VT *)nullptr, one);
+  // the column record's scales go to a spare control slot; the single-pair
+  // kernels read theirs from the state
+  hipLaunchKernelGGL(k_s2_beta, dim3(1), dim3(256), 0, stream, 1, bw->s2c, st, bw->ctrl, one);
+}
+
+bool sparse_second_single(rd_graph g, int32_t precision, void *U1, void *U2, LzState *st, hipStream_t stream) {
+  BatchWork *bw = batch_get(g);
+  if (!s2_reserve(g, bw, 1, stream)) return false;
+  // one column: the step pays while its scatter costs less than one dense
+  // single-pair iteration, which gathers nnz vector entries (8-byte gathers
+  // pulling whole lines): taken as nnz / 64 entries
+  const int64_t ecap = std::max<int64_t>(1, std::min<int64_t>(g->nnz / 64, g->nnz * 8 / 128));
+  if (precision == RD_F64)
+    single_second_t<double>(g, bw, (const double *)U1, (double *)U2, st, ecap, stream);
+  else
+    single_second_t<float>(g, bw, (const float *)U1, (float *)U2, st, ecap, stream);
+  RD_HIP(hipGetLastError());
+  return true;
 }
 
 // The three vector blocks of a run: q_{i-1}, q_i and the block the next

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(const double *__res
 
 // q_1 = (e_s/d_s - e_t/d_t)/sqrt(c), c = 1/d_s + 1/d_t (v_1 of Algorithm 3 in the scaled basis).
 template <typename VT>
-__global__ void k_init(int32_t n, VT *__restrict__ U, VT *__restrict__ U1,
+__global__ void k_init(int32_t n, VT *__restrict__ U, VT *__restrict__ U1, VT *__restrict__ U2,
                        const double *__restrict__ deg, int32_t s, int32_t t, double tol,
                        int32_t max_iters, int32_t fixed_k, int32_t delay, int32_t err_mode,
                        LzState *__restrict__ st) {
@@ -301,6 +301,7 @@ __global__ void k_init(int32_t n, VT *__restrict__ U, VT *__restrict__ U1,
     if (i == t) x = -rc / deg[t];
     U[i] = (VT)x;
     U1[i] = VT(0);
+    U2[i] = VT(0);  // the sparse second iteration writes w_2 into a zero vector
     if (i == 0) {
       LzState S;
       state_start(S, s, t, c, tol, max_iters, fixed_k, delay, err_mode, 0);
@@ -447,14 +448,29 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
                         double *tr_rhat) {
   PlainWork *pw = plain_get(g);
   hipLaunchKernelGGL(k_init<VT>, dim3((g->n + 255) / 256), dim3(256), 0, st, g->n, (VT *)pw->U[0],
-                     (VT *)pw->U[1], g->deg, s, t, eps, o.max_iters, o.fixed_k, o.delay, o.err_mode,
-                     pw->st);
+                     (VT *)pw->U[1], (VT *)pw->U[2], g->deg, s, t, eps, o.max_iters, o.fixed_k, o.delay,
+                     o.err_mode, pw->st);
   hipLaunchKernelGGL(k_first<VT>, dim3(1), dim3(256), 0, st, g->row_ptr, g->col,
                      (const double *)g->w64, g->deg, (VT *)pw->U[1], pw->st, tr_alpha, tr_beta, tr_rhat);
   RD_HIP(hipGetLastError());
   const int cap = o.fixed_k > 0 ? o.fixed_k : o.max_iters;
   // iteration 1 is done; the dense iterations start from U[1] (w_1) and U[0] (q_1)
   int done_iters = 1, prv = 0, cur = 1, nxt = 2;
+  // the second iteration from the support of q_2 (not with re-orthogonalisation
+  // or a trace, which records every iteration's scalars): then the dense
+  // iterations start from U[2] (w_2) and U[1] (w_1)
+  if (o.reorth == 0 && !tr_alpha && !(o.flags & RD_NO_SPARSE2) && cap >= 2 &&
+      sparse_second_single(g, sizeof(VT) == 8 ? RD_F64 : RD_F32, pw->U[1], pw->U[2], pw->st, st)) {
+    RD_HIP(hipMemcpyAsync(pw->st_host, pw->st, sizeof(LzState), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    if (pw->st_host->k == 2) {
+      done_iters = 2;
+      prv = 1;
+      cur = 2;
+      nxt = 0;
+    }
+  }
+  const int sparse_iters = done_iters;
   int chunk = o.fixed_k > 0 ? o.fixed_k - 1 : std::max(4, std::min(pw->last_k, 64));
   for (;;) {
     const int todo = std::min(chunk, cap - done_iters);
@@ -474,9 +490,9 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
     chunk = std::min(2 * chunk, 256);
   }
   const LzState &S = *pw->st_host;
-  // launches after the stopping iteration returned at once: count the first k
-  // (iteration 1 has no sparse product: the products of iterations 2..k did work)
-  if (o.flags & RD_PROFILE) g->timer[1].resolve((size_t)std::max(0, S.k - 1));
+  // launches after the stopping iteration returned at once: the dense
+  // products of iterations sparse_iters + 1 .. k did work
+  if (o.flags & RD_PROFILE) g->timer[1].resolve((size_t)std::max(0, S.k - sparse_iters));
   int32_t status = S.status;
   if (status == LZ_RUNNING) status = LZ_NOT_CONVERGED;  // cap reached while still running
   out->r = S.rhat;

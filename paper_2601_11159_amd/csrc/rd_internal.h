@@ -154,6 +154,9 @@ void plain_run(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o
 
 // batched path (lanczos_batch.hip)
 void batch_free(rd_graph g);
+// the sparse second iteration of a single-pair run (see lanczos_batch.hip);
+// false when its buffers are not available
+bool sparse_second_single(rd_graph g, int32_t precision, void *U1, void *U2, LzState *st, hipStream_t stream);
 
 // one workgroup per pair for graphs whose two vectors fit in LDS (lanczos_small.hip)
 bool small_eligible(rd_graph g, const rd_options &o);

@@ -235,3 +235,28 @@ def test_sparse2_iteration_cap_at_the_sparse_step():
     assert np.any(a["status"] == rd.RD_E_NOT_CONVERGED)
     mask = s != t
     np.testing.assert_allclose(a["r"][mask], b["r"][mask], rtol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["grid", "power_law", "weighted", "tree"])
+@pytest.mark.parametrize("prec,tol,bar", [(rd.RD_F64, 1e-10, 1e-8), (rd.RD_F32, 1e-5, 2e-3)])
+def test_sparse2_single_pair_path(name, prec, tol, bar):
+    # rd_query takes the sparse second iteration too: against the dense truth,
+    # and against the same query with a dense second product (fixed k)
+    g = GRAPHS[name]
+    s, t = _pairs(g, 12, seed=54)
+    G = rd.RDGraph(g.n, g.u, g.v, g.w)
+    o = dict(precision=prec, flags=rd.RD_GENERAL_PATH)
+    od = dict(precision=prec, flags=rd.RD_GENERAL_PATH | rd.RD_NO_SPARSE2)
+    for p in range(len(s)):
+        a = G.query(int(s[p]), int(t[p]), tol, rd.rd_default_options(**o))
+        if s[p] == t[p]:
+            assert a.r == 0.0
+            continue
+        truth = D.rd_all(g, s[p:p + 1], t[p:p + 1])[0]
+        assert a.status == rd.RD_OK
+        assert abs(a.r - truth) / truth <= bar
+        for k in (2, 3, 6):
+            x = G.query(int(s[p]), int(t[p]), tol, rd.rd_default_options(fixed_k=k, **o))
+            y = G.query(int(s[p]), int(t[p]), tol, rd.rd_default_options(fixed_k=k, **od))
+            assert x.iters == y.iters
+            assert x.r == pytest.approx(y.r, rel=1e-11 if prec == rd.RD_F64 else 1e-5)
