@@ -70,19 +70,20 @@ typedef enum {
                                the width (repeatedly, down to 16), so a tail of slow pairs does
                                not pay for idle columns. Results differ only by rounding. */
 
-#define RD_NO_SPARSE2 0x20u /* rd_options.flags: rd_query and rd_query_batch run the second
-                               Lanczos iteration of every pair as a dense product (rd_query
-                               takes the sparse step below when the scatter has at most
-                               nnz/64 entries, and not for rd_query_trace).
-                               By default (precision either, reorth 0), a pair whose second
-                               product touches few adjacency entries computes it from the
-                               support of q_2 alone, N(s) u N(t) u {s, t}: each entry
-                               (u, v), u in that support, adds w_uv w_1[u] / d_v to v's
-                               sum in 64-bit fixed point (integer sums do not depend on the
-                               order, so results stay the same from run to run), and the
-                               pair joins the dense iterations at the third (with the
-                               potentials' second terms, for rd_grad_edges and refine, also
-                               written on that support). Results differ only by rounding. */
+#define RD_NO_SPARSE2 0x20u /* rd_options.flags: run the second Lanczos iteration of every
+                               pair as a dense product. By default (precision either,
+                               reorth 0), a pair whose second product touches few adjacency
+                               entries computes it from the support of q_2 alone,
+                               N(s) u N(t) u {s, t}: each entry (u, v), u in that support,
+                               adds w_uv w_1[u] / d_v to v's sum in 64-bit fixed point
+                               (integer sums do not depend on the order, so results stay the
+                               same from run to run), and the pair joins the dense iterations
+                               at the third. rd_query_batch, rd_grad_edges and refine (which
+                               also write the potentials' second terms on that support) take
+                               the step when the scatter costs less than a dense column of the
+                               autotuned product; rd_query when it has at most nnz/64
+                               entries; rd_query_trace never. Results differ only by
+                               rounding. */
 
 /* weight / vector dtypes */
 #define RD_F64 0
