@@ -471,7 +471,12 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
     }
   }
   const int sparse_iters = done_iters;
-  int chunk = o.fixed_k > 0 ? o.fixed_k - 1 : std::max(4, std::min(pw->last_k, 64));
+  // iterations enqueued between two looks at the state: first what the
+  // previous query needed (a launch after the stop still dispatches every
+  // workgroup of the product before returning, about 0.3 ms on a 4M-node
+  // graph), then 2, then doubling for long runs
+  int chunk = o.fixed_k > 0 ? o.fixed_k - done_iters : std::max(1, std::min(pw->last_k, 64) - done_iters);
+  bool first_chunk = true;
   for (;;) {
     const int todo = std::min(chunk, cap - done_iters);
     for (int j = 0; j < todo; ++j) {
@@ -487,7 +492,8 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
     RD_HIP(hipMemcpyAsync(pw->st_host, pw->st, sizeof(LzState), hipMemcpyDeviceToHost, st));
     RD_HIP(hipStreamSynchronize(st));
     if (pw->st_host->status != LZ_RUNNING || done_iters >= cap) break;
-    chunk = std::min(2 * chunk, 256);
+    chunk = first_chunk ? 2 : std::min(2 * chunk, 256);
+    first_chunk = false;
   }
   const LzState &S = *pw->st_host;
   // launches after the stopping iteration returned at once: the dense
@@ -499,7 +505,7 @@ static void plain_run_t(rd_graph g, int32_t s, int32_t t, double eps, const rd_o
   out->err_est = S.err_est;
   out->iters = S.k;
   out->status = status_of(status);
-  pw->last_k = std::max(4, S.k);
+  pw->last_k = std::max(2, S.k);
 }
 
 void plain_run(rd_graph g, int32_t s, int32_t t, double eps, const rd_options &o, hipStream_t st,
