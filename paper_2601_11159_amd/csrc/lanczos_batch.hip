@@ -790,20 +790,65 @@ __device__ __forceinline__ double segment_sum(double x) {
   return x;
 }
 
+// Eight segment sums at once (LPR >= 8 lanes): the first three butterfly
+// stages each hand half of the values to the partner lane, so every stage
+// moves half as many values as the one before; the rest sum one value. The
+// total of value k ends in the lanes whose bits LPR/2, LPR/4, LPR/8 spell k;
+// the lane cl = k * LPR / 8 holds it.
+template <int LPR>
+__device__ __forceinline__ double segment_sums8(const double (&a)[8], int cl) {
+  double v4[4], v2[2];
+  {
+    constexpr int o = LPR / 2;
+    const bool up = cl & o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double keep = up ? a[i + 4] : a[i];
+      const double give = up ? a[i] : a[i + 4];
+      v4[i] = keep + __shfl_xor(give, o, 64);
+    }
+  }
+  {
+    constexpr int o = LPR / 4;
+    const bool up = cl & o;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double keep = up ? v4[i + 2] : v4[i];
+      const double give = up ? v4[i] : v4[i + 2];
+      v2[i] = keep + __shfl_xor(give, o, 64);
+    }
+  }
+  double x;
+  {
+    constexpr int o = LPR / 8;
+    const bool up = cl & o;
+    const double keep = up ? v2[1] : v2[0];
+    const double give = up ? v2[0] : v2[1];
+    x = keep + __shfl_xor(give, o, 64);
+  }
+#pragma unroll
+  for (int off = LPR / 16; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 // Edge gradient for the pairs held in the columns of X (the accumulated
-// potentials in the scaled basis: phi_p = sqrt(c_p) X[:, p]):
-//   gacc[e] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair.
-// One row segment (LPR lanes over the columns) per edge chunk; four edges in
-// flight per segment; FP64 sums in a fixed order.
+// potentials in the scaled basis: phi_p = sqrt(c_p) X[:, p]), for the
+// adjacency entry a = (u, v > u) of every edge:
+//   gacc[a] += -sum_p cw[p] (X[u, p] - X[v, p])^2,  cw[p] = grad_r[pair] * c_pair.
+// The accumulator is in adjacency order, so a chunk's words are contiguous;
+// k_gacc_out applies the edge ids once per call. One row segment (LPR lanes
+// over the columns) per edge chunk; EU edges in flight per segment; FP64 sums
+// in a fixed order.
 // gate != nullptr: run only when *gate == B (a full block of harvested potentials).
 template <typename PT, int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
     int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ eid, const PT *__restrict__ X, const double *__restrict__ cw,
-    double *__restrict__ gacc, const int32_t *__restrict__ gate) {
+    const PT *__restrict__ X, const double *__restrict__ cw, double *__restrict__ gacc,
+    const int32_t *__restrict__ gate) {
   if (gate && *gate != B) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
+  constexpr int EU = 8;  // one lane per edge writes its sum (a segment has >= 16 lanes)
   using XV = VecN<double, VEC>;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int sub = lane / S::LPR, cl = lane % S::LPR, c0 = cl * VEC;
@@ -817,25 +862,27 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
     const int32_t u = ch.x, pe = ch.z;
     const XV xu = vload_f64<PT, VEC>(X + (size_t)u * B + c0);
     int32_t p = ch.y;
-    for (; p + 4 <= pe; p += 4) {
-      XV xv[4];
+    for (; p + EU <= pe; p += EU) {
+      XV xv[EU];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) xv[k] = vload_f64<PT, VEC>(X + (size_t)col[p + k] * B + c0);
-      double sk[4];
+      for (int k = 0; k < EU; ++k) xv[k] = vload_f64<PT, VEC>(X + (size_t)col[p + k] * B + c0);
+      // lane cl = k * LPR / 8 writes edge k's sum
+      constexpr int WS = S::LPR / EU;
+      const bool writer = cl % WS == 0;
+      const int32_t kw = cl / WS;
+      const double g0 = writer ? gacc[p + kw] : 0.0;  // loaded with the gathers
+      double a[EU];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double a = 0.0;
+      for (int k = 0; k < EU; ++k) {
+        a[k] = 0.0;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           const double d = xu.v[v] - xv[k].v[v];
-          a += w[v] * d * d;
+          a[k] += w[v] * d * d;
         }
-        sk[k] = segment_sum<S::LPR>(a);
       }
-      if (cl < 4) {
-        const double mine = cl == 0 ? sk[0] : cl == 1 ? sk[1] : cl == 2 ? sk[2] : sk[3];
-        gacc[eid[p + cl]] -= mine;
-      }
+      const double mine = segment_sums8<S::LPR>(a, cl);
+      if (writer) gacc[p + kw] = g0 - mine;
     }
     for (; p < pe; ++p) {
       const XV xv = vload_f64<PT, VEC>(X + (size_t)col[p] * B + c0);
@@ -846,7 +893,7 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
         a += w[v] * d * d;
       }
       a = segment_sum<S::LPR>(a);
-      if (cl == 0) gacc[eid[p]] -= a;
+      if (cl == 0) gacc[p] -= a;
     }
   }
 }
@@ -924,9 +971,14 @@ __global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restric
   out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
 }
 
-__global__ void k_to_float(int64_t m, const double *__restrict__ a, float *__restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) b[i] = (float)a[i];
+// grad_w in caller edge order from the adjacency-order accumulator (one
+// thread per edge chunk).
+__global__ void k_gacc_out(int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ eid,
+                           const double *__restrict__ gacc, float *__restrict__ grad_w) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nch) return;
+  const int4 ch = chunk[i];
+  for (int32_t p = ch.y; p < ch.z; ++p) grad_w[eid[p]] = (float)gacc[p];
 }
 
 // beta_{i+1} of every running column and the next scales.
@@ -1629,7 +1681,7 @@ struct BatchWork {
   void *P = nullptr, *Xp = nullptr;
   void *Xf = nullptr;  // gradient harvest mode: n x B finished potentials
   size_t pot_bytes = 0;
-  double *gacc = nullptr;  // [m]
+  double *gacc = nullptr;  // [nnz]: edge gradient by adjacency entry (upper entries used)
   double *cw = nullptr;    // [256]
   LzState *st = nullptr;
   ColCtrl *ctrl = nullptr;
@@ -2005,8 +2057,8 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
   if (prm.gmode == GRAD_HARVEST) {
     // a full block of harvested potentials: its edge pass, then the slots are free
     hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                       (const int4 *)g->echunk, g->col, g->eid, (const VT *)bw->Xf,
-                       (const double *)bw->cw, bw->gacc, (const int32_t *)(bw->qstate + 4));
+                       (const int4 *)g->echunk, g->col, (const VT *)bw->Xf, (const double *)bw->cw, bw->gacc,
+                       (const int32_t *)(bw->qstate + 4));
     hipLaunchKernelGGL(k_harvest_reset, dim3(1), dim3(256), 0, st, B, bw->qstate, bw->cw);
   }
   if (prm.reorth > 0) {
@@ -2212,11 +2264,11 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     bw->pot_bytes = need;
   }
   if (!refine && !bw->Xf) bw->Xf = dev_alloc(bw->pot_bytes);
-  if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->m * sizeof(double));
+  if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->nnz * sizeof(double));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
   edge_chunks(g, st);
   if (!refine) {
-    RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->m * sizeof(double), st));
+    RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->nnz * sizeof(double), st));
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xf, 0, need, st));
@@ -2228,18 +2280,18 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     // the last, partly filled harvest block (unused slots have weight zero)
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (prof) {
-      // chunks, column and edge ids of the upper entries, the accumulator
-      // read and written, the potential block read once
-      ev = g->timer[2].next(16.0 * g->nch + 8.0 * (double)g->m + 16.0 * (double)g->m +
+      // chunks, column ids of the upper entries, the accumulator read and
+      // written, the potential block read once
+      ev = g->timer[2].next(16.0 * g->nch + 4.0 * (double)g->m + 16.0 * (double)g->m +
                             (double)sizeof(VT) * B * (double)g->n + 8.0 * B);
       RD_HIP(hipEventRecord(ev.first, st));
     }
     hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                       (const int4 *)g->echunk, g->col, g->eid, (const VT *)bw->Xf,
-                       (const double *)bw->cw, bw->gacc, (const int32_t *)nullptr);
+                       (const int4 *)g->echunk, g->col, (const VT *)bw->Xf, (const double *)bw->cw, bw->gacc,
+                       (const int32_t *)nullptr);
     if (prof) RD_HIP(hipEventRecord(ev.second, st));
-    hipLaunchKernelGGL(k_to_float, dim3(cdiv(g->m, 256)), dim3(256), 0, st, g->m,
-                       (const double *)bw->gacc, grad_w);
+    hipLaunchKernelGGL(k_gacc_out, dim3(cdiv(g->nch, 256)), dim3(256), 0, st, g->nch, (const int4 *)g->echunk,
+                       g->eid, (const double *)bw->gacc, grad_w);
     RD_HIP(hipGetLastError());
     if (prof) {
       RD_HIP(hipStreamSynchronize(st));
