@@ -857,8 +857,13 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
   for (int v = 0; v < VEC; ++v) w[v] = cw[c0 + v];
   const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
   const int nwv = gridDim.x * (SHORT_THREADS / 64);
-  for (int32_t ic = gw * S::RPW + sub; ic < nch; ic += nwv * S::RPW) {
-    const int4 ch = chunk[ic];
+  const int32_t stride = nwv * S::RPW;
+  int32_t ic = gw * S::RPW + sub;
+  int4 nx = ic < nch ? chunk[ic] : make_int4(0, 0, 0, 0);
+  for (; ic < nch; ic += stride) {
+    // the next chunk's bounds load while this one is processed
+    const int4 ch = nx;
+    if (ic + stride < nch) nx = chunk[ic + stride];
     const int32_t u = ch.x, pe = ch.z;
     const XV xu = vload_f64<PT, VEC>(X + (size_t)u * B + c0);
     int32_t p = ch.y;
