@@ -319,16 +319,27 @@ __global__ __launch_bounds__(LONG_THREADS) void k_spmm_long(
   VT acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
+  // UNR gathers in flight per lane (as in k_spmm_short), and the column ids of
+  // the next UNR entries loaded while those gathers run: a hub row's sub-row
+  // walks hundreds of entries, so its dependent loads set the launch's length
+  constexpr int UNR = sizeof(VT) * VEC >= 32 ? 4 : 8;
   int32_t p = pb + g;
-  for (; p + 3 * NG < pe; p += 4 * NG) {
-    int32_t ci[4];
+  int32_t ci[UNR];
+  if (p + (UNR - 1) * NG < pe) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ci[k] = col[p + k * NG];
-    V x[4];
+    for (int k = 0; k < UNR; ++k) ci[k] = col[p + k * NG];
+  }
+  for (; p + (UNR - 1) * NG < pe; p += UNR * NG) {
+    V x[UNR];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = vload<VT, VEC>(Ucur + (size_t)ci[k] * B + c0);
+    for (int k = 0; k < UNR; ++k) x[k] = vload<VT, VEC>(Ucur + (size_t)ci[k] * B + c0);
+    const int32_t pn = p + UNR * NG;
+    if (pn + (UNR - 1) * NG < pe) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < UNR; ++k) ci[k] = col[pn + k * NG];
+    }
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
       const VT wk = WEIGHTED ? w[p + k * NG] : VT(1);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += WEIGHTED ? wk * x[k].v[v] : x[k].v[v];
