@@ -245,7 +245,10 @@ rd_status rd_batch_schedule(rd_graph g, int32_t *wave_nnz, int32_t *long_deg);
  * (rd_result[npairs]). grad_w is float[m] in edge-list order, accumulated in
  * FP64. When o->flags has RD_DEVICE_PTRS, s, t, grad_r, fwd and grad_w are
  * device pointers. block_width 0 is autotuned; refine is ignored. Errors as
- * for rd_query_batch; grad_w == NULL is RD_E_ARG.
+ * for rd_query_batch; grad_w == NULL is RD_E_ARG. Device memory kept on the
+ * handle besides rd_query_batch's: three more n x width blocks in the vector
+ * precision (search directions, potentials, finished potentials) and an FP64
+ * accumulator of 8 bytes per adjacency entry (16 bytes per edge).
  */
 rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t,
                         const double *grad_r, double eps, const rd_options *o, rd_result *fwd,
