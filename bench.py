@@ -45,7 +45,8 @@ WORKLOADS = {
 }
 # further workloads, one JSON line each (not the default line)
 OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
-                   "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs"]
+                   "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs",
+                   "grid_64x64_100pairs_power_method"]
 
 
 def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
@@ -262,6 +263,100 @@ def run_other(name, args):
                                    "sample": f"{len(vals)} pairs, numpy Algorithm 3 forward at 1e-6"},
                      parity={"euler_identity_rel_err": abs(euler + float(fwd['r'].sum())) / float(fwd['r'].sum()),
                              "forward_max_rel_err_vs_oracle": float(np.max(np.abs(fwd['r'][:len(vals)] - vals) / vals))})
+    elif name == "grid_64x64_100pairs_power_method":
+        # the Power Method (Algorithm 1) against Lanczos at equal error (1e-8)
+        import scipy.sparse as sps
+        import scipy.sparse.linalg as spl
+        g = I.grid(64, 64)
+        s, t = I.uniform_pairs(g.n, 100, seed=1)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        f64 = dict(precision=rd.RD_F64, block_width=128)
+        ref = G.query_batch(s, t, 1e-12, rd.rd_default_options(**f64))["r"]
+        target = 1e-8
+
+        def pm_err(l):
+            r = G.power_method(s, t, l, rd.rd_default_options(**f64))["r"]
+            return float(np.max(np.abs(r - ref) / ref))
+
+        hi = 1024
+        while pm_err(hi) > target:
+            hi *= 2
+        lo = hi // 2
+        while hi - lo > max(16, hi // 64):
+            mid = (lo + hi) // 2
+            if pm_err(mid) > target:
+                lo = mid
+            else:
+                hi = mid
+        l_pm = hi
+        log(f"  Power Method reaches {target:g} at l = {l_pm}")
+        # value: the single-workgroup path (vectors and CSR in LDS, all steps in one launch)
+        G.power_method(s[:8], t[:8], 64, rd.rd_default_options(**f64))
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = G.power_method(s, t, l_pm, rd.rd_default_options(**f64))
+        torch.cuda.synchronize()
+        pdt = time.time() - t0
+        # beside it: the same l on the batched product kernels (k_spmm_short timed)
+        gopts = rd.rd_default_options(flags=rd.RD_PROFILE | rd.RD_GENERAL_PATH, **f64)
+        G.power_method(s[:8], t[:8], 64, gopts)
+        G.kernel_stats(0)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        gout = G.power_method(s, t, l_pm, gopts)
+        torch.cuda.synchronize()
+        gdt = time.time() - t0
+        ms, nl, b = G.kernel_stats(0)
+        avg = ms / max(nl, 1)
+        lz = G.query_batch(s, t, target, rd.rd_default_options(**f64))
+        bq, bout, broof, bdt = _batch_rate(G, rd, s, t, target, rd.rd_default_options(**f64), steps=3)
+        # kappa = 2 / mu_2 of the normalised Laplacian (shift-invert for the two smallest eigenvalues)
+        w = np.ones(g.m)
+        W = sps.coo_matrix((np.concatenate([w, w]), (np.concatenate([g.u, g.v]), np.concatenate([g.v, g.u]))),
+                           shape=(g.n, g.n)).tocsr()
+        isd = 1.0 / np.sqrt(np.asarray(W.sum(axis=1)).ravel())
+        Ln = sps.identity(g.n) - sps.diags(isd) @ W @ sps.diags(isd)
+        mu = np.sort(spl.eigsh(Ln.tocsc(), k=3, sigma=-1e-3, which="LM", return_eigenvectors=False))
+        kappa = 2.0 / mu[1]
+        # cpu_baseline: the oracle's Algorithm 1 at the same l on a sample of the pairs
+        from threadpoolctl import threadpool_limits
+        from oracle import power as PMO
+        P, d = PMO.transition_matrix(g)
+        vals, secs = [], 0.0
+        with threadpool_limits(limits=1):
+            for p in range(len(s)):
+                t1 = time.time()
+                vals.append(PMO.power_method(g, int(s[p]), int(t[p]), l_pm, P=P, d=d))
+                secs += time.time() - t1
+                if secs > 15.0:
+                    break
+        k = len(vals)
+        line = _line("queries/s", len(s) / pdt, 1, 1, pdt * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 100, "eps_rel": target,
+                      "path": f"rd_power_method, FP64, one workgroup per pair (k_pm_small), l = {l_pm} "
+                              f"products per pair (the least l, to within {max(16, l_pm // 64)}, whose results "
+                              f"are all within {target:g} of batched Lanczos at 1e-12)"},
+                     batched_product_path={"value": round(len(s) / gdt, 3), "unit": "queries/s",
+                                           "max_abs_diff_vs_value_path": float(np.max(np.abs(gout["r"] - out["r"])))},
+                     iterations={"power_method_l": l_pm, "lanczos_mean_k": float(lz["iters"].mean()),
+                                 "lanczos_max_k": int(lz["iters"].max()),
+                                 "ratio_l_over_k": round(l_pm / float(lz["iters"].mean()), 1),
+                                 "kappa": round(kappa, 1), "sqrt_kappa": round(float(np.sqrt(kappa)), 1)},
+                     lanczos_batched_fp64={"value": round(bq, 2), "unit": "queries/s",
+                                           "speedup_over_power_method": round(bq * pdt / len(s), 1)},
+                     roofline={"kernel": "k_spmm_short (the Power Method step on the batched product, width 128; "
+                                         "the value path runs from LDS)",
+                               "bound": "hbm", "achieved": round(b / (avg * 1e-3) / 1e9, 1) if nl else None,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if nl else None,
+                               "traffic": None, "avg_launch_ms": round(avg, 4), "launches": nl,
+                               "alg_bytes_per_launch": b,
+                               "note": "4,096-node graph: L2-resident; 64 wavefronts per product launch, "
+                                       "latency-bound"},
+                     cpu_baseline={"value": round(k / secs, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"{k} of the 100 pairs, numpy Algorithm 1 with the same l"},
+                     parity={"max_rel_err_vs_oracle": float(np.max(np.abs(out["r"][:k] - np.array(vals)) / np.array(vals))),
+                             "max_rel_err_vs_lanczos_1e-12": float(np.max(np.abs(out["r"] - ref) / ref))})
     else:
         raise SystemExit(f"unknown workload {name}")
     print(json.dumps(line), flush=True)

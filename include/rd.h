@@ -255,6 +255,28 @@ rd_status rd_grad_edges(rd_graph g, int32_t npairs, const int32_t *s, const int3
                         float *grad_w);
 
 /*
+ * Power Method (Algorithm 1, Section 2.2) for npairs pairs (s[p], t[p]):
+ *   r_bar = sum_{i=0}^{l} r_i(s) / (2 d_s) - r_i(t) / (2 d_t),
+ *   r_0 = e_s - e_t,  r_{i+1} = (I/2 + P/2) r_i,  P = A D^{-1},
+ * the series of Eq. er_laylor_expansion cut after l + 1 terms; the Power
+ * Method theorem gives |r_bar - r| <= eps for l = 2 kappa log(kappa / eps).
+ * out[p].r = r_bar, out[p].err_est = the last term added, out[p].iters = l
+ * (the number of products), out[p].status = RD_OK. Vectors in o->precision
+ * (FP32 or FP64), the sum in FP64. When both n-vectors fit in one
+ * workgroup's LDS (and RD_GENERAL_PATH is not set), one workgroup runs all l
+ * steps of a pair; otherwise B pairs at a time run on the batched product
+ * kernels. Options: precision, block_width (batched runs; 0: the width
+ * rd_tune_width picks), RD_DEVICE_PTRS (s, t, out are device memory),
+ * RD_GENERAL_PATH, RD_PROFILE (batched runs: the first 64 products of each
+ * group are timed for rd_kernel_stats which = 0).
+ * l < 0, ids outside [0, n) (checked on the device) or an unsupported
+ * block_width return RD_E_ARG; s == t gives 0. Device memory: the vector
+ * blocks of rd_query_batch (kept on the handle).
+ */
+rd_status rd_power_method(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, int32_t l,
+                          const rd_options *o, rd_result *out);
+
+/*
  * Diagnostic: timing of the sparse-product launches recorded by calls made
  * with RD_PROFILE in rd_options.flags, since the previous rd_kernel_stats call
  * (which resets the counters). which = 0: the batched product over the rows

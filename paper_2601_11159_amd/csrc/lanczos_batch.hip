@@ -2486,6 +2486,105 @@ static int32_t autotune_width(rd_graph g, BatchWork *bw, int prec, int32_t npair
   return bw->tuned[prec];
 }
 
+// ---------------------------------------------------------------------------
+// Power Method (Algorithm 1) for B pairs at a time on the batched product.
+// With x = D^{-1} r, the lazy step r <- (I/2 + P/2) r with P = A D^{-1} reads
+// x <- x/2 + D^{-1} A x / 2: the product kernels with column scale 1/2 and
+// coefficient -1/2 on the previous-vector operand, which is x itself. Before
+// each step the sum takes r(s)/(2 d_s) - r(t)/(2 d_t) = (x(s) - x(t)) / 2.
+
+// Column controls, sums and start vectors x_0 = e_s / d_s - e_t / d_t of one
+// group (X zeroed before; columns >= cnt stay zero).
+template <typename VT, int B>
+__global__ void k_pm_init(int32_t cnt, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt,
+                          const double *__restrict__ deg, ColCtrl *__restrict__ ctrl, VT *__restrict__ X,
+                          double *__restrict__ sums) {
+  const int j = threadIdx.x;
+  if (j >= B) return;
+  ColCtrl c{};
+  c.sig = 0.5;
+  c.pc = -0.5;
+  c.hslot = -1;
+  ctrl[j] = c;
+  sums[j] = 0.0;
+  sums[B + j] = 0.0;
+  if (j < cnt) {
+    const int32_t s = ps[j], t = pt[j];
+    X[(size_t)s * B + j] = (VT)(1.0 / deg[s]);
+    X[(size_t)t * B + j] -= (VT)(1.0 / deg[t]);  // s == t leaves zero
+  }
+}
+
+// sums[j] += (x(s_j) - x(t_j)) / 2 in FP64; sums[B + j] keeps the last term.
+template <typename VT, int B>
+__global__ void k_pm_acc(int32_t cnt, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt,
+                         const VT *__restrict__ X, double *__restrict__ sums) {
+  const int j = threadIdx.x;
+  if (j >= cnt) return;
+  const double term = 0.5 * ((double)X[(size_t)ps[j] * B + j] - (double)X[(size_t)pt[j] * B + j]);
+  sums[j] += term;
+  sums[B + j] = term;
+}
+
+template <int B>
+__global__ void k_pm_out(int32_t cnt, int32_t l, const double *__restrict__ sums, rd_result *__restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= cnt) return;
+  rd_result r;
+  r.r = sums[j];
+  r.err_est = sums[B + j];
+  r.iters = l;
+  r.status = RD_OK;
+  out[j] = r;
+}
+
+template <typename VT, int B>
+static void pm_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps, const int32_t *pt,
+                     int32_t l, rd_result *out, double *sums, hipStream_t st, bool prof) {
+  batch_reserve(g, bw, B, sizeof(VT));
+  const size_t bytes = (size_t)g->n * B * sizeof(VT);
+  const int32_t *gate = bw->qstate + 3;  // the constant 1
+  constexpr int32_t PROF_STEPS = 64;    // products timed per group under RD_PROFILE
+  for (int32_t p0 = 0; p0 < npairs; p0 += B) {
+    const int32_t cnt = std::min<int32_t>(B, npairs - p0);
+    VT *cur = (VT *)bw->X[0], *nxt = (VT *)bw->X[1];
+    RD_HIP(hipMemsetAsync(cur, 0, bytes, st));
+    hipLaunchKernelGGL((k_pm_init<VT, B>), dim3(1), dim3(256), 0, st, cnt, ps + p0, pt + p0, g->deg,
+                       bw->ctrl, cur, sums);
+    for (int32_t i = 0;; ++i) {
+      hipLaunchKernelGGL((k_pm_acc<VT, B>), dim3(1), dim3(256), 0, st, cnt, ps + p0, pt + p0,
+                         (const VT *)cur, sums);
+      if (i == l) break;
+      const bool tm = prof && i < PROF_STEPS;
+      if (g->unit)
+        launch_spmm<VT, B, false>(g, bw, cur, cur, nxt, st, gate, tm);
+      else
+        launch_spmm<VT, B, true>(g, bw, cur, cur, nxt, st, gate, tm);
+      std::swap(cur, nxt);
+    }
+    hipLaunchKernelGGL((k_pm_out<B>), dim3(1), dim3(256), 0, st, cnt, l, (const double *)sums, out + p0);
+    RD_HIP(hipGetLastError());
+    if (prof) {
+      RD_HIP(hipStreamSynchronize(st));
+      g->timer[0].resolve(g->timer[0].used);
+    }
+  }
+}
+
+template <typename VT>
+static void pm_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
+                        const int32_t *pt, int32_t l, rd_result *out, double *sums, hipStream_t st,
+                        bool prof) {
+  switch (B) {
+    case 16: return pm_run_t<VT, 16>(g, bw, npairs, ps, pt, l, out, sums, st, prof);
+    case 32: return pm_run_t<VT, 32>(g, bw, npairs, ps, pt, l, out, sums, st, prof);
+    case 64: return pm_run_t<VT, 64>(g, bw, npairs, ps, pt, l, out, sums, st, prof);
+    case 128: return pm_run_t<VT, 128>(g, bw, npairs, ps, pt, l, out, sums, st, prof);
+    case 256: return pm_run_t<VT, 256>(g, bw, npairs, ps, pt, l, out, sums, st, prof);
+  }
+  throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
+}
+
 extern "C" {
 
 rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, double eps,
@@ -2561,6 +2660,75 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
     if (!dp) {
       RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
     }
+    RD_HIP(hipStreamSynchronize(st));
+    for (void *p : owned) dev_free(p);
+    return RD_OK;
+  } catch (const RdError &e) {
+    (void)hipDeviceSynchronize();
+    for (void *p : owned) dev_free(p);
+    g->err = e.msg;
+    return e.code;
+  }
+}
+
+rd_status rd_power_method(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, int32_t l,
+                          const rd_options *o, rd_result *out) {
+  if (!g || npairs < 0 || l < 0 || (npairs > 0 && (!s || !t || !out))) return RD_E_ARG;
+  std::vector<void *> owned;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    if (npairs == 0) return RD_OK;
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, o);
+    BatchWork *bw = batch_get(g);
+    const bool dp = opt.flags & RD_DEVICE_PTRS;
+    const int32_t *ds = s, *dt = t;
+    rd_result *dout = out;
+    if (!dp) {
+      int32_t *tmp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(tmp);
+      RD_HIP(hipMemcpyAsync(tmp, s, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      RD_HIP(hipMemcpyAsync(tmp + npairs, t, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      ds = tmp;
+      dt = tmp + npairs;
+      dout = (rd_result *)dev_alloc((size_t)npairs * sizeof(rd_result));
+      owned.push_back(dout);
+    }
+    RD_HIP(hipMemsetAsync(bw->flag, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->n, ds, dt,
+                       bw->flag);
+    int32_t bad = 0;
+    RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+    if (g->perm) {
+      int32_t *mp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(mp);
+      hipLaunchKernelGGL(k_map_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->perm, ds,
+                         dt, mp, mp + npairs);
+      RD_HIP(hipGetLastError());
+      ds = mp;
+      dt = mp + npairs;
+    }
+    int32_t B = opt.block_width;
+    RD_REQUIRE(B == 0 || B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
+               "block_width must be 0 or one of 16, 32, 64, 128, 256");
+    if (small_eligible(g, opt)) {
+      // both vectors fit in LDS: one workgroup per pair runs all l steps
+      pm_small_run(g, npairs, ds, dt, l, opt, st, dout);
+    } else {
+      if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
+      double *sums = (double *)dev_alloc(2 * 256 * sizeof(double));
+      owned.push_back(sums);
+      const bool prof = opt.flags & RD_PROFILE;
+      if (opt.precision == RD_F64)
+        pm_dispatch<double>(g, bw, B, npairs, ds, dt, l, dout, sums, st, prof);
+      else
+        pm_dispatch<float>(g, bw, B, npairs, ds, dt, l, dout, sums, st, prof);
+    }
+    if (!dp)
+      RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
     RD_HIP(hipStreamSynchronize(st));
     for (void *p : owned) dev_free(p);
     return RD_OK;

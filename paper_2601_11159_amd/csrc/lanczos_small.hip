@@ -180,6 +180,68 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small(
   }
 }
 
+// Power Method (Algorithm 1) for one pair per workgroup. With x = D^{-1} r
+// in LDS, each step is x <- x/2 + D^{-1} A x / 2 (P = A D^{-1}); before each
+// step thread 0 adds r(s)/(2 d_s) - r(t)/(2 d_t) = (x(s) - x(t)) / 2 to the
+// FP64 sum. A block barrier separates the steps; the two buffers alternate.
+template <typename VT, bool WEIGHTED, bool CSR_LDS>
+__global__ __launch_bounds__(SMALL_THREADS) void k_pm_small(
+    int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const VT *__restrict__ w, const VT *__restrict__ invdeg, const double *__restrict__ deg,
+    int32_t npairs, const int32_t *__restrict__ ps, const int32_t *__restrict__ pt, int32_t l,
+    rd_result *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  VT *xa = reinterpret_cast<VT *>(lds_raw);
+  VT *xb = xa + n;
+  const int32_t pair = blockIdx.x;
+  if (pair >= npairs) return;
+  const int32_t s = ps[pair], t = pt[pair];
+  if (s == t) {
+    if (threadIdx.x == 0) out[pair] = rd_result{0.0, 0.0, l, RD_OK};
+    return;
+  }
+  const int32_t *RP = row_ptr;
+  const int32_t *CL = col;
+  const VT *WL = w;
+  if constexpr (CSR_LDS) {
+    int32_t *rp_l = reinterpret_cast<int32_t *>(xb + n);
+    int32_t *col_l = rp_l + (n + 1);
+    for (int32_t i = threadIdx.x; i <= n; i += SMALL_THREADS) rp_l[i] = row_ptr[i];
+    for (int32_t i = threadIdx.x; i < nnz; i += SMALL_THREADS) col_l[i] = col[i];
+    if constexpr (WEIGHTED) {
+      const size_t off = ((size_t)(n + 1 + nnz) * 4 + sizeof(VT) - 1) / sizeof(VT) * sizeof(VT);
+      VT *w_l = reinterpret_cast<VT *>(reinterpret_cast<unsigned char *>(rp_l) + off);
+      for (int32_t i = threadIdx.x; i < nnz; i += SMALL_THREADS) w_l[i] = w[i];
+      WL = w_l;
+    }
+    RP = rp_l;
+    CL = col_l;
+  }
+  const VT xs = (VT)(1.0 / deg[s]), xt = (VT)(-1.0 / deg[t]);
+  for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) xa[r] = r == s ? xs : (r == t ? xt : VT(0));
+  __syncthreads();
+  double sum = 0.0, last = 0.0;
+  VT *cur = xa, *nxt = xb;
+  for (int32_t i = 0;; ++i) {
+    if (threadIdx.x == 0) {
+      last = 0.5 * ((double)cur[s] - (double)cur[t]);
+      sum += last;
+    }
+    if (i == l) break;
+    for (int32_t r = threadIdx.x; r < n; r += SMALL_THREADS) {
+      VT acc = 0;
+      const int32_t pe = RP[r + 1];
+      for (int32_t p = RP[r]; p < pe; ++p) acc += WEIGHTED ? WL[p] * cur[CL[p]] : cur[CL[p]];
+      nxt[r] = VT(0.5) * acc * invdeg[r] + VT(0.5) * cur[r];
+    }
+    __syncthreads();
+    VT *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  if (threadIdx.x == 0) out[pair] = rd_result{sum, last, l, RD_OK};
+}
+
 }  // namespace
 
 // Largest dynamic LDS per workgroup the small path may use.
@@ -244,6 +306,37 @@ void small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt,
       small_launch<float, false>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
     else
       small_launch<float, true>(g, npairs, ps, pt, s0, t0, eps, o, st, out, tr_alpha, tr_beta, tr_rhat);
+  }
+  RD_HIP(hipGetLastError());
+}
+
+template <typename VT, bool WEIGHTED>
+static void pm_small_launch(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t l,
+                            hipStream_t st, rd_result *out) {
+  const bool csr = small_lds_bytes(g, sizeof(VT), true) <= small_lds_limit(g);
+  const size_t lds = small_lds_bytes(g, sizeof(VT), csr);
+  const VT *w = (const VT *)(sizeof(VT) == 8 ? (const void *)g->w64 : (const void *)g->w32);
+  const VT *id = (const VT *)(sizeof(VT) == 8 ? (const void *)g->invdeg : (const void *)g->invdeg32);
+  if (csr)
+    hipLaunchKernelGGL((k_pm_small<VT, WEIGHTED, true>), dim3(npairs), dim3(SMALL_THREADS), lds, st, g->n,
+                       (int32_t)g->nnz, g->row_ptr, g->col, WEIGHTED ? w : (const VT *)nullptr, id, g->deg,
+                       npairs, ps, pt, l, out);
+  else
+    hipLaunchKernelGGL((k_pm_small<VT, WEIGHTED, false>), dim3(npairs), dim3(SMALL_THREADS), lds, st, g->n,
+                       (int32_t)g->nnz, g->row_ptr, g->col, WEIGHTED ? w : (const VT *)nullptr, id, g->deg,
+                       npairs, ps, pt, l, out);
+}
+
+// Power Method for graphs whose two vectors fit in LDS: one workgroup per pair.
+void pm_small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t l,
+                  const rd_options &o, hipStream_t st, rd_result *out) {
+  if (npairs <= 0) return;
+  if (o.precision == RD_F64) {
+    if (g->unit) pm_small_launch<double, false>(g, npairs, ps, pt, l, st, out);
+    else pm_small_launch<double, true>(g, npairs, ps, pt, l, st, out);
+  } else {
+    if (g->unit) pm_small_launch<float, false>(g, npairs, ps, pt, l, st, out);
+    else pm_small_launch<float, true>(g, npairs, ps, pt, l, st, out);
   }
   RD_HIP(hipGetLastError());
 }

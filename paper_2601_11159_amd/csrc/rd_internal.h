@@ -163,3 +163,6 @@ bool small_eligible(rd_graph g, const rd_options &o);
 void small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t s0,
                int32_t t0, double eps, const rd_options &o, hipStream_t st, rd_result *out,
                double *tr_alpha, double *tr_beta, double *tr_rhat);
+// the Power Method (Algorithm 1) on the same single-workgroup layout
+void pm_small_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_t *pt, int32_t l,
+                  const rd_options &o, hipStream_t st, rd_result *out);

@@ -38,7 +38,7 @@ RD_F32 = 1
 EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
-    "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule",
+    "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule", "rd_power_method",
 ]
 
 
@@ -98,8 +98,9 @@ def load(path: str = LIB_PATH):
     lib.rd_query_trace.argtypes = [vp, i32, i32, i32, P(RdOptions), vp, vp, vp, P(i32)]
     lib.rd_query_batch.argtypes = [vp, i32, vp, vp, dbl, P(RdOptions), vp]
     lib.rd_grad_edges.argtypes = [vp, i32, vp, vp, vp, dbl, P(RdOptions), vp, vp]
+    lib.rd_power_method.argtypes = [vp, i32, vp, vp, i32, P(RdOptions), vp]
     for f in (lib.rd_init_graph, lib.rd_set_weights, lib.rd_graph_info, lib.rd_query,
-              lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges):
+              lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges, lib.rd_power_method):
         f.restype = ctypes.c_int
     lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
     lib.rd_tune_width.restype = ctypes.c_int
@@ -298,6 +299,30 @@ class RDGraph:
                                    ctypes.byref(_stream_of(opts, ds)), pout)
         if rc != RD_OK:
             self._raise(rc, "rd_query_batch")
+        del ks, kt
+        return res
+
+    def power_method(self, s, t, l: int, opts: Optional[RdOptions] = None, out=None):
+        """Power Method (Algorithm 1) with l products per pair. Host arrays ->
+        numpy structured array of results; device tensors -> results written
+        to `out` (a torch uint8 CUDA tensor of 24*npairs bytes)."""
+        npairs = int(len(s))
+        ps, ds, ks = _ptr(s, np.int32, npairs)
+        pt, dt, kt = _ptr(t, np.int32, npairs)
+        if ds != dt:
+            raise ValueError("s and t must both be host or both be device memory")
+        if ds:
+            if out is None:
+                raise ValueError("device pair lists need a device `out` buffer")
+            pout = out.data_ptr()
+            res = out
+        else:
+            res = np.zeros(npairs, dtype=RESULT_DTYPE)
+            pout = res.ctypes.data
+        rc = load().rd_power_method(self._h, npairs, ps, pt, int(l),
+                                    ctypes.byref(_stream_of(opts, ds)), pout)
+        if rc != RD_OK:
+            self._raise(rc, "rd_power_method")
         del ks, kt
         return res
 
