@@ -46,7 +46,7 @@ WORKLOADS = {
 # further workloads, one JSON line each (not the default line)
 OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
                    "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs",
-                   "grid_64x64_100pairs_power_method"]
+                   "grid_64x64_100pairs_power_method", "weighted_chung_lu_n1M_potentials_256pairs"]
 
 
 def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
@@ -263,6 +263,62 @@ def run_other(name, args):
                                    "sample": f"{len(vals)} pairs, numpy Algorithm 3 forward at 1e-6"},
                      parity={"euler_identity_rel_err": abs(euler + float(fwd['r'].sum())) / float(fwd['r'].sum()),
                              "forward_max_rel_err_vs_oracle": float(np.max(np.abs(fwd['r'][:len(vals)] - vals) / vals))})
+    elif name == "weighted_chung_lu_n1M_potentials_256pairs":
+        # electric potentials (Section 6.3) of C5's pairs, left in device memory
+        g = I.chung_lu(1_000_000, 2.1, 20.0, 2)
+        w = I.lognormal_weights(g.m, 0.0, 1.0, seed=5)
+        s, t = I.uniform_pairs(g.n, 256, seed=6)
+        G = rd.RDGraph(g.n, g.u, g.v, w, reorder=True)
+        eps = 1e-6
+        opts = rd.rd_default_options(precision=rd.RD_F32, block_width=64, flags=rd.RD_PROFILE)
+        ds = torch.tensor(s, dtype=torch.int32, device="cuda")
+        dt = torch.tensor(t, dtype=torch.int32, device="cuda")
+        out = torch.zeros(24 * len(s), dtype=torch.uint8, device="cuda")
+        phi = torch.empty((len(s), g.n), dtype=torch.float64, device="cuda")
+        G.potentials(ds[:64], dt[:64], eps, opts, out=out[: 24 * 64], phi=phi[:64])
+        G.kernel_stats(0)
+        steps = max(1, args.steps)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(steps):
+            G.potentials(ds, dt, eps, opts, out=out, phi=phi)
+        torch.cuda.synchronize()
+        pdt = (time.time() - t0) / steps
+        ms, nl, b = G.kernel_stats(0)
+        avg = ms / max(nl, 1)
+        res = np.frombuffer(out.cpu().numpy().tobytes(), dtype=rd.RESULT_DTYPE)
+        # cpu_baseline: the oracle's Lanczos potentials (Algorithm 5's estimate) at the same
+        # iteration counts, on a sample of the pairs, against the GPU's
+        from threadpoolctl import threadpool_limits
+        from oracle import lanczos as LZ
+        gw = I.Graph(g.n, g.u, g.v, w)
+        A, d = LZ.normalized_adjacency(gw)
+        perr, secs, k = [], 0.0, 0
+        with threadpool_limits(limits=1):
+            for p in range(2):
+                t1 = time.time()
+                run = LZ.lanczos_rd(gw, int(s[p]), int(t[p]), k=int(res["iters"][p]), keep_vectors=True, A=A, d=d)
+                ph = LZ.potentials_lanczos(gw, int(s[p]), int(t[p]), run, d)
+                secs += time.time() - t1
+                ph = ph - ph.mean()
+                gp = phi[p].cpu().numpy()
+                perr.append(float(np.abs(gp - ph).max() / np.abs(ph).max()))
+                k += 1
+        line = _line("pairs/s (potentials)", len(s) / pdt, steps, 1, pdt * 1e3, "f32",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": eps,
+                      "path": "rd_potentials, FP32 vectors, width 64, groups of 64 pairs, phi (FP64, 256 x n) "
+                              "left in device memory",
+                      "node_order": "decreasing degree (RD_REORDER)"},
+                     roofline={"kernel": "k_spmm_short (batched FP32 sparse product over the short rows)",
+                               "bound": "hbm", "achieved": round(b / (avg * 1e-3) / 1e9, 1) if nl else None,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if nl else None,
+                               "traffic": None, "avg_launch_ms": round(avg, 4), "launches": nl,
+                               "alg_bytes_per_launch": b},
+                     cpu_baseline={"value": round(k / secs, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"{k} pairs, numpy Algorithm 3 with its vectors kept and the potential "
+                                             "of Algorithm 5, at the GPU's iteration counts"},
+                     parity={"phi_max_rel_err_vs_oracle": max(perr), "mean_iters": float(res["iters"].mean())})
     elif name == "grid_64x64_100pairs_power_method":
         # the Power Method (Algorithm 1) against Lanczos at equal error (1e-8)
         import scipy.sparse as sps

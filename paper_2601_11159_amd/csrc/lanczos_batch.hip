@@ -987,6 +987,45 @@ __global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restric
   out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
 }
 
+// Per-column partial sums of X over the rows (fixed order, as the products).
+template <typename VT, int B>
+__global__ __launch_bounds__(SHORT_THREADS) void k_col_reduce(int32_t n, const VT *__restrict__ X,
+                                                            double *__restrict__ part, int32_t ldp) {
+  using S = Shape<B>;
+  constexpr int VEC = S::VEC;
+  __shared__ double sm[(SHORT_THREADS / 64) * B];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int sub = lane / S::LPR, c0 = (lane % S::LPR) * VEC;
+  double acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
+  const int gw = blockIdx.x * (SHORT_THREADS / 64) + wid;
+  const int nwv = gridDim.x * (SHORT_THREADS / 64);
+  for (int32_t r = gw * S::RPW + sub; r < n; r += nwv * S::RPW) {
+    const VecN<VT, VEC> x = vload<VT, VEC>(X + (size_t)r * B + c0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += (double)x.v[v];
+  }
+  block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
+}
+
+// phi_p = Pi sqrt(c_p) X[:, j] in the caller's node order (perm: caller id ->
+// row; nullptr: the identity), one row of n values per pair; colsum[j] is the
+// column's sum, so the mean is removed (phi sums to zero, as L^+ b does).
+template <typename VT, int B>
+__global__ void k_pot_out(int32_t n, const int32_t *__restrict__ perm, const LzState *__restrict__ st,
+                          const VT *__restrict__ X, const double *__restrict__ colsum,
+                          double *__restrict__ phi) {
+  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (u >= n) return;
+  const LzState &S = st[j];
+  if (S.pair < 0) return;
+  const double sc = sqrt(S.c);
+  const int32_t r = perm ? perm[u] : u;
+  phi[(size_t)S.pair * n + u] = sc * ((double)X[(size_t)r * B + j] - colsum[j] / n);
+}
+
 // grad_w in caller edge order from the adjacency-order accumulator (one
 // thread per edge chunk).
 __global__ void k_gacc_out(int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ eid,
@@ -2265,7 +2304,7 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
 template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
-                       rd_result *out, float *grad_w, hipStream_t st, bool prof) {
+                       rd_result *out, float *grad_w, hipStream_t st, bool prof, double *phi = nullptr) {
   const bool refine = grad_w == nullptr;
   batch_reserve(g, bw, B, sizeof(VT));
   const size_t need = (size_t)g->n * B * sizeof(VT);  // potentials stored like the vectors
@@ -2335,6 +2374,16 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
                        bw->cw, bw->qstate + 3);
     hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
                        (const VT *)bw->Xp, (const double *)bw->cw, out + off);
+    if (phi) {
+      // the group's potentials, mean removed, in the caller's node order
+      hipLaunchKernelGGL((k_col_reduce<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                         (const VT *)bw->Xp, bw->part, bw->ldp);
+      hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
+                         bw->cw, bw->qstate + 3);
+      hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
+                         (const int32_t *)g->perm, (const LzState *)bw->st, (const VT *)bw->Xp,
+                         (const double *)bw->cw, phi + (size_t)off * g->n);
+    }
     RD_HIP(hipGetLastError());
   }
 }
@@ -2342,13 +2391,14 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
 template <typename VT>
 static void grad_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npairs, const int32_t *ps,
                           const int32_t *pt, const double *grad_r, const RunParams &prm,
-                          rd_result *out, float *grad_w, hipStream_t st, bool prof) {
+                          rd_result *out, float *grad_w, hipStream_t st, bool prof,
+                          double *phi = nullptr) {
   switch (B) {
-    case 16: return grad_run_t<VT, 16>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
-    case 32: return grad_run_t<VT, 32>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
-    case 64: return grad_run_t<VT, 64>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
-    case 128: return grad_run_t<VT, 128>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
-    case 256: return grad_run_t<VT, 256>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof);
+    case 16: return grad_run_t<VT, 16>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof, phi);
+    case 32: return grad_run_t<VT, 32>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof, phi);
+    case 64: return grad_run_t<VT, 64>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof, phi);
+    case 128: return grad_run_t<VT, 128>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof, phi);
+    case 256: return grad_run_t<VT, 256>(g, bw, npairs, ps, pt, grad_r, prm, out, grad_w, st, prof, phi);
   }
   throw RdError{RD_E_ARG, "block_width must be one of 16, 32, 64, 128, 256"};
 }
@@ -2729,6 +2779,82 @@ rd_status rd_power_method(rd_graph g, int32_t npairs, const int32_t *s, const in
     }
     if (!dp)
       RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    for (void *p : owned) dev_free(p);
+    return RD_OK;
+  } catch (const RdError &e) {
+    (void)hipDeviceSynchronize();
+    for (void *p : owned) dev_free(p);
+    g->err = e.msg;
+    return e.code;
+  }
+}
+
+rd_status rd_potentials(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, double eps,
+                        const rd_options *o, rd_result *out, double *phi) {
+  if (!g || npairs < 0 || (npairs > 0 && (!s || !t || !phi))) return RD_E_ARG;
+  std::vector<void *> owned;
+  try {
+    g->err.clear();
+    rd_options opt = resolve_options(g, o);
+    RD_REQUIRE(opt.fixed_k > 0 || eps > 0.0, "eps must be > 0 unless fixed_k is set");
+    if (npairs == 0) return RD_OK;
+    RD_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, o);
+    BatchWork *bw = batch_get(g);
+    const bool dp = opt.flags & RD_DEVICE_PTRS;
+    const int32_t *ds = s, *dt = t;
+    rd_result *dout = out;
+    double *dphi = phi;
+    const size_t phi_bytes = (size_t)npairs * g->n * sizeof(double);
+    if (!dp) {
+      int32_t *tmp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(tmp);
+      RD_HIP(hipMemcpyAsync(tmp, s, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      RD_HIP(hipMemcpyAsync(tmp + npairs, t, npairs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      ds = tmp;
+      dt = tmp + npairs;
+      dphi = (double *)dev_alloc(phi_bytes);
+      owned.push_back(dphi);
+    }
+    if (!dp || !out) {
+      dout = (rd_result *)dev_alloc((size_t)npairs * sizeof(rd_result));
+      owned.push_back(dout);
+    }
+    RD_HIP(hipMemsetAsync(bw->flag, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->n, ds, dt,
+                       bw->flag);
+    int32_t bad = 0;
+    RD_HIP(hipMemcpyAsync(&bad, bw->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    RD_HIP(hipStreamSynchronize(st));
+    RD_REQUIRE(!bad, "pair node ids must be in [0, n)");
+    if (g->perm) {
+      int32_t *mp = (int32_t *)dev_alloc(2 * (size_t)npairs * sizeof(int32_t));
+      owned.push_back(mp);
+      hipLaunchKernelGGL(k_map_pairs, dim3(cdiv(npairs, 256)), dim3(256), 0, st, npairs, g->perm, ds,
+                         dt, mp, mp + npairs);
+      RD_HIP(hipGetLastError());
+      ds = mp;
+      dt = mp + npairs;
+    }
+    int32_t B = opt.block_width;
+    RD_REQUIRE(B == 0 || B == 16 || B == 32 || B == 64 || B == 128 || B == 256,
+               "block_width must be 0 or one of 16, 32, 64, 128, 256");
+    if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
+    RD_HIP(hipMemsetAsync(dphi, 0, phi_bytes, st));
+    // groups of B pairs with potentials (the refinement mode), r as the FP64 energy
+    RunParams prm{eps,       opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth,
+                  GRAD_NONE, nullptr,       (opt.flags & RD_NO_SPARSE2) ? 0 : 1, 0};
+    const bool prof = opt.flags & RD_PROFILE;
+    if (opt.precision == RD_F64)
+      grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof, dphi);
+    else
+      grad_dispatch<float>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof, dphi);
+    if (!dp) {
+      RD_HIP(hipMemcpyAsync(phi, dphi, phi_bytes, hipMemcpyDeviceToHost, st));
+      if (out)
+        RD_HIP(hipMemcpyAsync(out, dout, (size_t)npairs * sizeof(rd_result), hipMemcpyDeviceToHost, st));
+    }
     RD_HIP(hipStreamSynchronize(st));
     for (void *p : owned) dev_free(p);
     return RD_OK;

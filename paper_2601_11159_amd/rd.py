@@ -39,6 +39,7 @@ EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
     "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule", "rd_power_method",
+    "rd_potentials",
 ]
 
 
@@ -99,8 +100,10 @@ def load(path: str = LIB_PATH):
     lib.rd_query_batch.argtypes = [vp, i32, vp, vp, dbl, P(RdOptions), vp]
     lib.rd_grad_edges.argtypes = [vp, i32, vp, vp, vp, dbl, P(RdOptions), vp, vp]
     lib.rd_power_method.argtypes = [vp, i32, vp, vp, i32, P(RdOptions), vp]
+    lib.rd_potentials.argtypes = [vp, i32, vp, vp, dbl, P(RdOptions), vp, vp]
     for f in (lib.rd_init_graph, lib.rd_set_weights, lib.rd_graph_info, lib.rd_query,
-              lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges, lib.rd_power_method):
+              lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges, lib.rd_power_method,
+              lib.rd_potentials):
         f.restype = ctypes.c_int
     lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
     lib.rd_tune_width.restype = ctypes.c_int
@@ -325,6 +328,33 @@ class RDGraph:
             self._raise(rc, "rd_power_method")
         del ks, kt
         return res
+
+    def potentials(self, s, t, eps: float = 1e-6, opts: Optional[RdOptions] = None, out=None, phi=None):
+        """Electric potentials of the pairs: (results, phi) with phi float64
+        [npairs, n] in the caller's node order, mean zero. Host arrays -> numpy
+        outputs; device tensors -> results into `out` (torch uint8, 24*npairs
+        bytes) and potentials into `phi` (torch float64 [npairs, n])."""
+        npairs = int(len(s))
+        ps, ds, ks = _ptr(s, np.int32, npairs)
+        pt, dt, kt = _ptr(t, np.int32, npairs)
+        if ds != dt:
+            raise ValueError("s and t must both be host or both be device memory")
+        if ds:
+            if out is None or phi is None:
+                raise ValueError("device pair lists need device `out` and `phi` buffers")
+            if tuple(phi.shape) != (npairs, self.n) or phi.dtype != __import__("torch").float64:
+                raise ValueError("phi must be a float64 tensor of shape [npairs, n]")
+            res, pout, pphi = out, out.data_ptr(), phi.data_ptr()
+        else:
+            res = np.zeros(npairs, dtype=RESULT_DTYPE)
+            phi = np.zeros((npairs, self.n), dtype=np.float64)
+            pout, pphi = res.ctypes.data, phi.ctypes.data
+        rc = load().rd_potentials(self._h, npairs, ps, pt, float(eps), ctypes.byref(_stream_of(opts, ds)),
+                                  pout, pphi)
+        if rc != RD_OK:
+            self._raise(rc, "rd_potentials")
+        del ks, kt
+        return res, phi
 
     def grad_edges(self, s, t, grad_r=None, eps: float = 1e-6, opts: Optional[RdOptions] = None,
                    fwd=None, grad_w=None):
