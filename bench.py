@@ -46,7 +46,8 @@ WORKLOADS = {
 # further workloads, one JSON line each (not the default line)
 OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
                    "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs",
-                   "grid_64x64_100pairs_power_method", "weighted_chung_lu_n1M_potentials_256pairs"]
+                   "grid_64x64_100pairs_power_method", "weighted_chung_lu_n1M_potentials_256pairs",
+                   "condition_numbers"]
 
 
 def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
@@ -319,6 +320,53 @@ def run_other(name, args):
                                    "sample": f"{k} pairs, numpy Algorithm 3 with its vectors kept and the potential "
                                              "of Algorithm 5, at the GPU's iteration counts"},
                      parity={"phi_max_rel_err_vs_oracle": max(perr), "mean_iters": float(res["iters"].mean())})
+    elif name == "condition_numbers":
+        # kappa_hat = 2 / (1 - theta_max) from the extreme Ritz value of a k-step
+        # deflated Lanczos run (a lower bound that rises to kappa), per graph
+        graphs = [("grid_64x64", lambda: (I.grid(64, 64), None), 400, False),
+                  ("chung_lu_n1M_g2.1_d20", lambda: (I.chung_lu(1_000_000, 2.1, 20.0, 2), None), 100, True),
+                  ("road_like_2000x2000", lambda: (I.road_like(2000, seed=3), None), 3000, False),
+                  ("chung_lu_n4M_g2.3_d32", lambda: (I.chung_lu(4_000_000, 2.3, 32.0, 4), None), 100, True),
+                  ("weighted_chung_lu_n1M", lambda: (I.chung_lu(1_000_000, 2.1, 20.0, 2), "w"), 100, True)]
+        rows = {}
+        t_all = time.time()
+        for gname, make, k, reorder in graphs:
+            g, wflag = make()
+            w = I.lognormal_weights(g.m, 0.0, 1.0, seed=5) if wflag else None
+            G = rd.RDGraph(g.n, g.u, g.v, w, reorder=reorder)
+            s, t = I.uniform_pairs(g.n, 1, seed=7)
+            t0 = time.time()
+            lo, hi, it = G.ritz_bounds(int(s[0]), int(t[0]), k, rd.rd_default_options(flags=rd.RD_PROFILE))
+            dt = time.time() - t0
+            _, hi2, _ = G.ritz_bounds(int(s[0]), int(t[0]), k // 2)
+            ms, nl, b = G.kernel_stats(1)
+            rows[gname] = {"k": it, "theta_min": lo, "theta_max": hi, "kappa_hat": round(2.0 / (1.0 - hi), 2),
+                           "kappa_hat_at_k_over_2": round(2.0 / (1.0 - hi2), 2), "seconds": round(dt, 3),
+                           "k_spmv_avg_ms": round(ms / max(nl, 1), 4)}
+            log(f"  {gname}: kappa_hat {rows[gname]['kappa_hat']} (k = {it})")
+            G.close()
+        total = time.time() - t_all
+        # the oracle's deflated Lanczos on the 64x64 grid at the same k
+        from threadpoolctl import threadpool_limits
+        from oracle import lanczos as LZ
+        g = I.grid(64, 64)
+        s, t = I.uniform_pairs(g.n, 1, seed=7)
+        A, d = LZ.normalized_adjacency(g)
+        with threadpool_limits(limits=1):
+            t0 = time.time()
+            run = LZ.lanczos_rd(g, int(s[0]), int(t[0]), k=400, A=A, d=d, reorth=1)
+            th = LZ.ritz_values(run)
+            osec = time.time() - t0
+        c1 = rows["grid_64x64"]
+        line = _line("kappa (lower bound, road-like 2000x2000)", rows["road_like_2000x2000"]["kappa_hat"], 1, 0,
+                     total * 1e3, "f64",
+                     {"workload": name, "graphs": rows,
+                      "path": "rd_ritz_bounds: k-step FP64 Lanczos from the pair (e_s, e_t) start vector with "
+                              "the null direction deflated, extreme eigenvalues of T_k by Sturm bisection"},
+                     cpu_baseline={"value": round(1.0 / osec, 3), "unit": "runs/s (64x64 grid, k = 400)", "cores": 1,
+                                   "kind": "oracle", "sample": "one deflated numpy Algorithm 3 run with its Ritz values"},
+                     parity={"grid_theta_max_abs_diff_vs_oracle": abs(c1["theta_max"] - float(th[-1])),
+                             "grid_theta_min_abs_diff_vs_oracle": abs(c1["theta_min"] - float(th[0]))})
     elif name == "grid_64x64_100pairs_power_method":
         # the Power Method (Algorithm 1) against Lanczos at equal error (1e-8)
         import scipy.sparse as sps

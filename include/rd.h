@@ -187,6 +187,24 @@ rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
                          double *alpha, double *beta, double *rhat, int32_t *iters);
 
 /*
+ * Extreme Ritz values of a k-step Lanczos run from the pair's start vector
+ * (Section 3): the smallest and largest eigenvalues theta_min, theta_max of
+ * the tridiagonal T_k of alpha_1..alpha_k and beta_2..beta_k (*iters = the
+ * steps done, fewer at an exact breakdown). v_1 is orthogonal to D^{1/2} 1,
+ * so both lie in [lambda_min(calA), lambda_2(calA)] (the Ritz-containment
+ * check of Assumption 1), theta_max rises towards lambda_2 as k grows, and
+ * kappa_hat = 2 / (1 - theta_max) is a lower bound of the condition number
+ * kappa = 2 / mu_2 (Section 2.1) that converges to it. The run always deflates
+ * u_1 = D^{1/2} 1 / sqrt(vol) (reorth >= 1): without it, rounding brings the
+ * eigenvalue-1 direction back in long runs and theta_max drifts to 1. The
+ * eigenvalues of T_k are found on the host by bisection on the Sturm count.
+ * Options as for rd_query_trace (precision, reorth 2 adds the local
+ * Gram-Schmidt pass). s == t, ids outside [0, n) or k < 1 return RD_E_ARG.
+ */
+rd_status rd_ritz_bounds(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_options *o,
+                         double *theta_min, double *theta_max, int32_t *iters);
+
+/*
  * Many pairs: npairs independent runs of Algorithm 3 advanced together as the
  * block columns of one sparse product per iteration; a column whose run stops
  * is retired and its slot refilled with the next pending pair (pairs with

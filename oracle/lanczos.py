@@ -191,6 +191,14 @@ def tridiag_matrix(alpha, beta) -> np.ndarray:
     return T
 
 
+def ritz_values(run: LanczosRun) -> np.ndarray:
+    """Eigenvalues of T_k (diagonal alpha_1..alpha_k, off-diagonal
+    beta_2..beta_k), the Ritz values of the run (Section 3), ascending."""
+    k = run.k
+    return sla.eigvalsh_tridiagonal(np.asarray(run.alpha[:k], dtype=np.float64),
+                                    np.asarray(run.beta[1:k], dtype=np.float64))
+
+
 def potentials_lanczos(g, s: int, t: int, run: LanczosRun, d) -> np.ndarray:
     """phi_hat = sqrt(1/d_s + 1/d_t) D^{-1/2} V (I - T)^{-1} e_1, the potential
     estimate of Algorithm 5, from a run made with keep_vectors=True."""

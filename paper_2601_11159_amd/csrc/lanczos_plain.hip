@@ -26,6 +26,7 @@
 // enqueue iterations ahead of the stopping decision.
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "lanczos_common.h"
@@ -590,3 +591,60 @@ rd_status rd_query_trace(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
 }
 
 }  // extern "C"
+
+// The smallest and largest eigenvalues of the symmetric tridiagonal matrix
+// with diagonal a[0..k) and off-diagonal b[0..k-1) (b[j] couples rows j and
+// j+1): bisection on the Sturm count, the number of negative pivots of the
+// LDL^T factorisation of T - x I, which equals the number of eigenvalues
+// below x.
+static int32_t sturm_below(const double *a, const double *b, int32_t k, double x) {
+  int32_t neg = 0;
+  double d = 1.0;
+  for (int32_t j = 0; j < k; ++j) {
+    d = a[j] - x - (j ? b[j - 1] * b[j - 1] / d : 0.0);
+    if (d == 0.0) d = -1e-300;  // a zero pivot counts as an eigenvalue at x
+    if (d < 0.0) ++neg;
+  }
+  return neg;
+}
+
+static double tridiag_eig(const double *a, const double *b, int32_t k, int32_t idx, double lo, double hi) {
+  // the idx-th smallest eigenvalue (0-based) in [lo, hi]
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, k, mid) > idx) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+extern "C" rd_status rd_ritz_bounds(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_options *o,
+                                    double *theta_min, double *theta_max, int32_t *iters) {
+  if (!g || !theta_min || !theta_max || !iters || k < 1) return RD_E_ARG;
+  rd_options o2;
+  try {
+    o2 = resolve_options(g, o);
+  } catch (const RdError &e) {
+    g->err = e.msg;
+    return e.code;
+  }
+  // without deflation, rounding brings back the direction D^{1/2} 1 of
+  // eigenvalue 1 in long runs and the top Ritz value drifts to 1
+  o2.reorth = std::max(o2.reorth, 1);
+  o2.max_iters = 0;
+  o2.fixed_k = 0;
+  std::vector<double> a(k), b(k), r(k);
+  const rd_status rc = rd_query_trace(g, s, t, k, &o2, a.data(), b.data(), r.data(), iters);
+  if (rc != RD_OK) return rc;
+  const int32_t kk = *iters;
+  // Gershgorin interval of T_k
+  double lo = 1e300, hi = -1e300;
+  for (int32_t j = 0; j < kk; ++j) {
+    const double rad = (j ? std::fabs(b[j - 1]) : 0.0) + (j + 1 < kk ? std::fabs(b[j]) : 0.0);
+    lo = std::min(lo, a[j] - rad);
+    hi = std::max(hi, a[j] + rad);
+  }
+  *theta_min = tridiag_eig(a.data(), b.data(), kk, 0, lo, hi);
+  *theta_max = tridiag_eig(a.data(), b.data(), kk, kk - 1, lo, hi);
+  return RD_OK;
+}

@@ -39,7 +39,7 @@ EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
     "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule", "rd_power_method",
-    "rd_potentials",
+    "rd_potentials", "rd_ritz_bounds",
 ]
 
 
@@ -101,9 +101,10 @@ def load(path: str = LIB_PATH):
     lib.rd_grad_edges.argtypes = [vp, i32, vp, vp, vp, dbl, P(RdOptions), vp, vp]
     lib.rd_power_method.argtypes = [vp, i32, vp, vp, i32, P(RdOptions), vp]
     lib.rd_potentials.argtypes = [vp, i32, vp, vp, dbl, P(RdOptions), vp, vp]
+    lib.rd_ritz_bounds.argtypes = [vp, i32, i32, i32, P(RdOptions), P(dbl), P(dbl), P(i32)]
     for f in (lib.rd_init_graph, lib.rd_set_weights, lib.rd_graph_info, lib.rd_query,
               lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges, lib.rd_power_method,
-              lib.rd_potentials):
+              lib.rd_potentials, lib.rd_ritz_bounds):
         f.restype = ctypes.c_int
     lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
     lib.rd_tune_width.restype = ctypes.c_int
@@ -328,6 +329,17 @@ class RDGraph:
             self._raise(rc, "rd_power_method")
         del ks, kt
         return res
+
+    def ritz_bounds(self, s: int, t: int, k: int, opts: Optional[RdOptions] = None):
+        """(theta_min, theta_max, iters) of a k-step Lanczos run from the pair's
+        start vector; kappa_hat = 2 / (1 - theta_max)."""
+        lo, hi, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        o = opts if opts is not None else rd_default_options()
+        rc = load().rd_ritz_bounds(self._h, int(s), int(t), int(k), ctypes.byref(o), ctypes.byref(lo),
+                                   ctypes.byref(hi), ctypes.byref(it))
+        if rc != RD_OK:
+            self._raise(rc, "rd_ritz_bounds")
+        return lo.value, hi.value, it.value
 
     def potentials(self, s, t, eps: float = 1e-6, opts: Optional[RdOptions] = None, out=None, phi=None):
         """Electric potentials of the pairs: (results, phi) with phi float64

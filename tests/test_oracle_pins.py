@@ -263,6 +263,18 @@ def test_lanczos_ritz_values_inside_spectrum():
     assert theta.min() >= lam[0] - 1e-12 and theta.max() <= lam[-2] + 1e-12
 
 
+def test_ritz_values_reach_the_spectrum_after_n_minus_one_steps():
+    # n - 1 steps span the space orthogonal to D^{1/2} 1 on a graph without
+    # symmetric degeneracies: the extreme Ritz values are lambda_min and lambda_2
+    g = I.random_connected(14, extra=20, seed=44, weighted=True)
+    A, d = LZ.normalized_adjacency(g)
+    lam = np.linalg.eigvalsh(A.toarray())
+    run = LZ.lanczos_rd(g, 2, 11, k=g.n - 1, A=A, d=d, reorth=1)
+    theta = LZ.ritz_values(run)
+    assert run.k == g.n - 1
+    assert abs(theta[0] - lam[0]) <= 1e-8 and abs(theta[-1] - lam[-2]) <= 1e-8
+
+
 def _cg_quadratic_forms(M, b, steps):
     """Textbook conjugate gradient on M x = b from x_0 = 0, returning b^T x_k
     for k = 1..steps (written here independently of the oracle)."""
