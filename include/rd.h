@@ -205,6 +205,26 @@ rd_status rd_ritz_bounds(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
                          double *theta_min, double *theta_max, int32_t *iters);
 
 /*
+ * Lanczos Push (Algorithm 4, Section 4.1) for npairs pairs, k iterations of
+ * the subset Lanczos recurrence with threshold eps >= 0: a nonzero entry
+ * v_i(u) is pushed along edge (u, v) only when |v_i(u)| > eps sqrt(d_u d_v)
+ * (Definition of AMV), and the alpha and beta terms are subtracted only on
+ * S_i = {u : |v_i(u)| > eps d_u}. out[p].r = r' = (1/d_s + 1/d_t) v_1^T V
+ * (I - T)^{-1} e_1, out[p].iters = the iterations done (fewer than k at an
+ * exact breakdown), out[p].err_est = 0, status RD_OK; s == t gives 0. With
+ * eps = 0 this is Algorithm 3 at k iterations. One workgroup per pair keeps
+ * the nonzero entries as lists over per-slot node arrays, so the work follows
+ * the pushed edges; results agree with the sequential algorithm to rounding
+ * (atomic FP64 sums), not bit for bit. FP64 throughout; options: the
+ * RD_DEVICE_PTRS flag (s, t, out device memory) and stream. Device memory:
+ * 40 bytes per node per concurrent pair (at most 512 pairs and 8 GB),
+ * allocated per call. npairs < 0, k < 1, eps < 0 or ids outside [0, n) return
+ * RD_E_ARG.
+ */
+rd_status rd_lanczos_push(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, int32_t k,
+                          double eps, const rd_options *o, rd_result *out);
+
+/*
  * Many pairs: npairs independent runs of Algorithm 3 advanced together as the
  * block columns of one sparse product per iteration; a column whose run stops
  * is retired and its slot refilled with the next pending pair (pairs with

@@ -39,7 +39,7 @@ EXPORTED = [
     "rd_default_options", "rd_init_graph", "rd_set_weights", "rd_graph_info", "rd_query",
     "rd_query_trace", "rd_query_batch", "rd_grad_edges", "rd_free_graph", "rd_status_string",
     "rd_last_error", "rd_kernel_stats", "rd_tune_width", "rd_batch_schedule", "rd_power_method",
-    "rd_potentials", "rd_ritz_bounds",
+    "rd_potentials", "rd_ritz_bounds", "rd_lanczos_push",
 ]
 
 
@@ -102,9 +102,10 @@ def load(path: str = LIB_PATH):
     lib.rd_power_method.argtypes = [vp, i32, vp, vp, i32, P(RdOptions), vp]
     lib.rd_potentials.argtypes = [vp, i32, vp, vp, dbl, P(RdOptions), vp, vp]
     lib.rd_ritz_bounds.argtypes = [vp, i32, i32, i32, P(RdOptions), P(dbl), P(dbl), P(i32)]
+    lib.rd_lanczos_push.argtypes = [vp, i32, vp, vp, i32, dbl, P(RdOptions), vp]
     for f in (lib.rd_init_graph, lib.rd_set_weights, lib.rd_graph_info, lib.rd_query,
               lib.rd_query_trace, lib.rd_query_batch, lib.rd_grad_edges, lib.rd_power_method,
-              lib.rd_potentials, lib.rd_ritz_bounds):
+              lib.rd_potentials, lib.rd_ritz_bounds, lib.rd_lanczos_push):
         f.restype = ctypes.c_int
     lib.rd_tune_width.argtypes = [vp, i32, i32, vp, P(i32)]
     lib.rd_tune_width.restype = ctypes.c_int
@@ -327,6 +328,21 @@ class RDGraph:
                                     ctypes.byref(_stream_of(opts, ds)), pout)
         if rc != RD_OK:
             self._raise(rc, "rd_power_method")
+        del ks, kt
+        return res
+
+    def lanczos_push(self, s, t, k: int, eps: float, opts: Optional[RdOptions] = None):
+        """Lanczos Push (Algorithm 4) for host pair arrays: numpy results."""
+        npairs = int(len(s))
+        ps, ds, ks = _ptr(s, np.int32, npairs)
+        pt, dt, kt = _ptr(t, np.int32, npairs)
+        if ds or dt:
+            raise ValueError("lanczos_push() takes host pair lists")
+        res = np.zeros(npairs, dtype=RESULT_DTYPE)
+        rc = load().rd_lanczos_push(self._h, npairs, ps, pt, int(k), float(eps),
+                                    ctypes.byref(_stream_of(opts, False)), res.ctypes.data)
+        if rc != RD_OK:
+            self._raise(rc, "rd_lanczos_push")
         del ks, kt
         return res
 
