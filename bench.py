@@ -47,7 +47,7 @@ WORKLOADS = {
 OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
                    "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs",
                    "grid_64x64_100pairs_power_method", "weighted_chung_lu_n1M_potentials_256pairs",
-                   "condition_numbers"]
+                   "condition_numbers", "road_like_2000x2000_lanczos_push"]
 
 
 def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
@@ -320,6 +320,51 @@ def run_other(name, args):
                                    "sample": f"{k} pairs, numpy Algorithm 3 with its vectors kept and the potential "
                                              "of Algorithm 5, at the GPU's iteration counts"},
                      parity={"phi_max_rel_err_vs_oracle": max(perr), "mean_iters": float(res["iters"].mean())})
+    elif name == "road_like_2000x2000_lanczos_push":
+        # Lanczos Push (Algorithm 4) on the road-like graph: k = 200 iterations at
+        # eps = 1e-4, beside batched Lanczos (Algorithm 3) at the same k
+        g = I.road_like(2000, seed=3)
+        s, t = I.uniform_pairs(g.n, 256, seed=3)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        k, eps = 200, 1e-4
+        G.lanczos_push(s[:4], t[:4], k, eps)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = G.lanczos_push(s, t, k, eps)
+        torch.cuda.synchronize()
+        pdt = time.time() - t0
+        lo = rd.rd_default_options(precision=rd.RD_F64, block_width=256, fixed_k=k, max_iters=k)
+        G.query_batch(s[:4], t[:4], 1e-4, lo)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        lz = G.query_batch(s, t, 1e-4, lo)
+        torch.cuda.synchronize()
+        ldt = time.time() - t0
+        # cpu_baseline: the oracle's Algorithm 4 on two of the pairs, with the
+        # share of nodes it touched and of edges it pushed along
+        from threadpoolctl import threadpool_limits
+        from oracle import push as LPO
+        W, d = LPO._adjacency(g)
+        perr, touched, pushes, secs = [], [], [], 0.0
+        with threadpool_limits(limits=1):
+            for p in range(2):
+                t1 = time.time()
+                run = LPO.lanczos_push(g, int(s[p]), int(t[p]), k, eps, W=W, d=d)
+                secs += time.time() - t1
+                perr.append(abs(out["r"][p] - run.r) / abs(run.r))
+                touched.append(run.touched / g.n)
+                pushes.append(run.pushes / (k * 2.0 * g.m))
+        line = _line("queries/s", len(s) / pdt, 1, 1, pdt * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "k": k, "eps_push": eps,
+                      "path": "rd_lanczos_push: one workgroup per pair, frontier lists over per-slot node arrays"},
+                     lanczos_fixed_k={"value": round(len(s) / ldt, 3), "unit": "queries/s",
+                                      "path": "rd_query_batch FP64, width 256, fixed k = 200"},
+                     push_vs_lanczos_same_k={"max_rel_diff": float(np.max(np.abs(out["r"] - lz["r"]) / lz["r"])),
+                                             "median_rel_diff": float(np.median(np.abs(out["r"] - lz["r"]) / lz["r"]))},
+                     locality={"nodes_touched_share": touched, "edge_pushes_share_of_k_full_products": pushes},
+                     cpu_baseline={"value": round(2 / secs, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                                   "sample": "2 pairs, numpy Algorithm 4 with the same k and eps"},
+                     parity={"max_rel_err_vs_oracle": float(max(perr))})
     elif name == "condition_numbers":
         # kappa_hat = 2 / (1 - theta_max) from the extreme Ritz value of a k-step
         # deflated Lanczos run (a lower bound that rises to kappa), per graph

@@ -217,7 +217,7 @@ rd_status rd_ritz_bounds(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
  * the pushed edges; results agree with the sequential algorithm to rounding
  * (atomic FP64 sums), not bit for bit. FP64 throughout; options: the
  * RD_DEVICE_PTRS flag (s, t, out device memory) and stream. Device memory:
- * 40 bytes per node per concurrent pair (at most 512 pairs and 8 GB),
+ * 40 bytes per node per concurrent pair (at most 512 pairs and 48 GB),
  * allocated per call. npairs < 0, k < 1, eps < 0 or ids outside [0, n) return
  * RD_E_ARG.
  */

@@ -5,7 +5,8 @@
 // read or written, so the work follows the pushed edges, not the graph size.
 //
 // Per iteration i (block barriers between the phases):
-//   push     a wavefront per frontier node u pushes w_uv v_i(u) / sqrt(d_u d_v)
+//   push     each frontier node u (a thread, or a wavefront for rows longer
+//            than 64 entries) pushes w_uv v_i(u) / sqrt(d_u d_v)
 //            to every neighbour v with |v_i(u)| > eps sqrt(d_u d_v) (Definition
 //            of AMV), FP64 atomic adds; each first touch of v appends it to the
 //            candidate list C (flag array);
@@ -31,7 +32,7 @@
 
 namespace {
 
-constexpr int PUSH_THREADS = 512;
+constexpr int PUSH_THREADS = 1024;
 constexpr int PUSH_WAVES = PUSH_THREADS / 64;
 
 template <bool WEIGHTED>
@@ -75,12 +76,28 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(
         hist[2 * k + i] = v1s * vcur[s] + v1t * vcur[t];
       }
       __syncthreads();
-      // push: one wavefront per frontier node, lanes over its neighbours
+      // push: a thread per frontier node with at most 64 entries, a wavefront
+      // (lanes over the entries) per longer row
+      for (int32_t idx = threadIdx.x; idx < nf; idx += PUSH_THREADS) {
+        const int32_t u = fcur[idx];
+        const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
+        if (pe - pb > 64) continue;
+        const double val = vcur[u], su = sqrt(deg[u]);
+        for (int32_t p = pb; p < pe; ++p) {
+          const int32_t v = col[p];
+          const double sq = su * sqrt(deg[v]);
+          if (fabs(val) > eps * sq) {
+            atomicAdd(&y[v], (WEIGHTED ? w[p] : 1.0) * val / sq);
+            if (atomicExch(&flag[v], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = v;
+          }
+        }
+      }
       for (int32_t idx = wid; idx < nf; idx += PUSH_WAVES) {
         const int32_t u = fcur[idx];
+        const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
+        if (pe - pb <= 64) continue;
         const double val = vcur[u], su = sqrt(deg[u]);
-        const int32_t pe = row_ptr[u + 1];
-        for (int32_t p = row_ptr[u] + lane; p < pe; p += 64) {
+        for (int32_t p = pb + lane; p < pe; p += 64) {
           const int32_t v = col[p];
           const double sq = su * sqrt(deg[v]);
           if (fabs(val) > eps * sq) {
@@ -192,7 +209,7 @@ static void push_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_
   if (npairs <= 0) return;
   const size_t n = (size_t)g->n;
   const size_t per_slot = n * (3 * sizeof(double) + 4 * sizeof(int32_t));
-  const size_t budget = (size_t)8 << 30;
+  const size_t budget = (size_t)48 << 30;  // of the 288 GB HBM
   int32_t slots = (int32_t)std::min<size_t>({(size_t)npairs, (size_t)512, std::max<size_t>(1, budget / per_slot)});
   double *va = (double *)dev_alloc(slots * n * sizeof(double));
   double *vb = (double *)dev_alloc(slots * n * sizeof(double));
