@@ -211,18 +211,32 @@ static void push_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_
   const size_t per_slot = n * (3 * sizeof(double) + 4 * sizeof(int32_t));
   const size_t budget = (size_t)48 << 30;  // of the 288 GB HBM
   int32_t slots = (int32_t)std::min<size_t>({(size_t)npairs, (size_t)512, std::max<size_t>(1, budget / per_slot)});
-  double *va = (double *)dev_alloc(slots * n * sizeof(double));
-  double *vb = (double *)dev_alloc(slots * n * sizeof(double));
-  double *yv = (double *)dev_alloc(slots * n * sizeof(double));
-  int32_t *fl = (int32_t *)dev_alloc(slots * n * sizeof(int32_t));
-  int32_t *la = (int32_t *)dev_alloc(slots * n * sizeof(int32_t));
-  int32_t *lb = (int32_t *)dev_alloc(slots * n * sizeof(int32_t));
-  int32_t *lc = (int32_t *)dev_alloc(slots * n * sizeof(int32_t));
-  double *hist = (double *)dev_alloc((size_t)slots * 4 * k * sizeof(double));
-  RD_HIP(hipMemsetAsync(va, 0, slots * n * sizeof(double), st));
-  RD_HIP(hipMemsetAsync(vb, 0, slots * n * sizeof(double), st));
-  RD_HIP(hipMemsetAsync(yv, 0, slots * n * sizeof(double), st));
-  RD_HIP(hipMemsetAsync(fl, 0, slots * n * sizeof(int32_t), st));
+  // every buffer is freed on return and on an exception alike
+  struct Bufs {
+    std::vector<void *> p;
+    ~Bufs() {
+      (void)hipDeviceSynchronize();  // no launch may still use them
+      for (void *x : p) dev_free(x);
+    }
+    void *get(size_t bytes) {
+      p.push_back(nullptr);
+      p.back() = dev_alloc(bytes);
+      return p.back();
+    }
+  } bufs;
+  const size_t sn = (size_t)slots * n;
+  double *va = (double *)bufs.get(sn * sizeof(double));
+  double *vb = (double *)bufs.get(sn * sizeof(double));
+  double *yv = (double *)bufs.get(sn * sizeof(double));
+  int32_t *fl = (int32_t *)bufs.get(sn * sizeof(int32_t));
+  int32_t *la = (int32_t *)bufs.get(sn * sizeof(int32_t));
+  int32_t *lb = (int32_t *)bufs.get(sn * sizeof(int32_t));
+  int32_t *lc = (int32_t *)bufs.get(sn * sizeof(int32_t));
+  double *hist = (double *)bufs.get((size_t)slots * 4 * k * sizeof(double));
+  RD_HIP(hipMemsetAsync(va, 0, sn * sizeof(double), st));
+  RD_HIP(hipMemsetAsync(vb, 0, sn * sizeof(double), st));
+  RD_HIP(hipMemsetAsync(yv, 0, sn * sizeof(double), st));
+  RD_HIP(hipMemsetAsync(fl, 0, sn * sizeof(int32_t), st));
   if (g->unit)
     hipLaunchKernelGGL((k_push<false>), dim3(slots), dim3(PUSH_THREADS), 0, st, g->n, g->row_ptr, g->col,
                        (const double *)nullptr, g->deg, npairs, ps, pt, k, eps, va, vb, yv, fl, la, lb, lc,
@@ -233,9 +247,6 @@ static void push_run(rd_graph g, int32_t npairs, const int32_t *ps, const int32_
                        hist, out);
   RD_HIP(hipGetLastError());
   RD_HIP(hipStreamSynchronize(st));
-  for (void *p : {(void *)va, (void *)vb, (void *)yv, (void *)fl, (void *)la, (void *)lb, (void *)lc,
-                  (void *)hist})
-    dev_free(p);
 }
 
 extern "C" rd_status rd_lanczos_push(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, int32_t k,
