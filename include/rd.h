@@ -214,8 +214,10 @@ rd_status rd_ritz_bounds(rd_graph g, int32_t s, int32_t t, int32_t k, const rd_o
  * exact breakdown), out[p].err_est = 0, status RD_OK; s == t gives 0. With
  * eps = 0 this is Algorithm 3 at k iterations. One workgroup per pair keeps
  * the nonzero entries as lists over per-slot node arrays, so the work follows
- * the pushed edges; results agree with the sequential algorithm to rounding
- * (atomic FP64 sums), not bit for bit. FP64 throughout; options: the
+ * the pushed edges. Each node's AMV sum runs in adjacency order and alpha,
+ * beta^2 are summed in fixed point, so results are the same bit for bit from
+ * call to call (and agree with the sequential algorithm to rounding). FP64
+ * throughout; options: the
  * RD_DEVICE_PTRS flag (s, t, out device memory) and stream. Device memory:
  * 40 bytes per node per concurrent pair (at most 512 pairs and 48 GB),
  * allocated per call. npairs < 0, k < 1, eps < 0 or ids outside [0, n) return

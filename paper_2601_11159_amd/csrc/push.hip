@@ -5,13 +5,14 @@
 // read or written, so the work follows the pushed edges, not the graph size.
 //
 // Per iteration i (block barriers between the phases):
-//   push     each frontier node u (a thread, or a wavefront for rows longer
-//            than 64 entries) pushes w_uv v_i(u) / sqrt(d_u d_v)
-//            to every neighbour v with |v_i(u)| > eps sqrt(d_u d_v) (Definition
-//            of AMV), FP64 atomic adds; each first touch of v appends it to the
-//            candidate list C (flag array);
-//   restrict v_{i+1} -= beta_i v_{i-1} on S_{i-1} = {u : |v_{i-1}(u)| > eps d_u};
-//            the nodes of S_{i-1} and S_i join C;
+//   targets  each frontier node u (a thread, or a wavefront for rows longer
+//            than 64 entries) marks every neighbour v with |v_i(u)| >
+//            eps sqrt(d_u d_v) (Definition of AMV); each first mark appends v to
+//            the candidate list C (flag array); the nodes of
+//            S_{i-1} = {u : |v_{i-1}(u)| > eps d_u} and S_i join C;
+//   sums     each candidate v pulls AMV(calA, v_i)(v) = sum over its pushing
+//            neighbours u of w_uv v_i(u) / sqrt(d_u d_v), in adjacency order, and
+//            subtracts beta_i v_{i-1}(v) when v is in S_{i-1};
 //   alpha    alpha_i = <v_{i+1}, v_i> over C;
 //   update   v_{i+1} -= alpha_i v_i on S_i; beta_{i+1}^2 = sum over C;
 //   rotate   v_{i+1} / beta_{i+1} on the nonzero entries of C becomes the next
@@ -21,8 +22,9 @@
 // <v_1, v_j> = v_1(s) v_j(s) + v_1(t) v_j(t) per iteration and a k x k
 // tridiagonal solve at the end (thread 0).
 //
-// The atomic adds make the summation order of AMV depend on scheduling:
-// results agree with the sequential algorithm to rounding, not bit for bit.
+// Every per-node sum runs in adjacency order and alpha, beta^2 are summed in
+// fixed point (integer words), so the order of the lists, which the atomics
+// that build them decide, changes nothing: runs are bitwise reproducible.
 
 #include <algorithm>
 #include <cmath>
@@ -35,6 +37,37 @@ namespace {
 constexpr int PUSH_THREADS = 1024;
 constexpr int PUSH_WAVES = PUSH_THREADS / 64;
 
+// Order-independent sums: a term x (|x| < 2^20) is split into integer words in
+// units of 2^-40 and 2^-80; integer addition does not depend on the order in
+// which the threads and lists deliver the terms.
+__device__ __forceinline__ void fx_add(double x, long long &hi, long long &lo) {
+  const double sx = x * 0x1p40;
+  const double h = floor(sx);
+  hi += (long long)h;
+  lo += (long long)rint((sx - h) * 0x1p40);
+}
+
+// Block total of the two words (every thread gets it), as a double.
+__device__ __forceinline__ double fx_block_total(long long hi, long long lo, long long *sm) {
+  for (int off = 32; off > 0; off >>= 1) {
+    hi += __shfl_xor(hi, off, 64);
+    lo += __shfl_xor(lo, off, 64);
+  }
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    sm[2 * wid] = hi;
+    sm[2 * wid + 1] = lo;
+  }
+  __syncthreads();
+  long long th = 0, tl = 0;
+  for (int wv = 0; wv < PUSH_WAVES; ++wv) {
+    th += sm[2 * wv];
+    tl += sm[2 * wv + 1];
+  }
+  return (double)th * 0x1p-40 + (double)tl * 0x1p-80;
+}
+
 template <bool WEIGHTED>
 __global__ __launch_bounds__(PUSH_THREADS) void k_push(
     int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -42,7 +75,7 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(
     const int32_t *__restrict__ ps, const int32_t *__restrict__ pt, int32_t k, double eps,
     double *va_all, double *vb_all, double *y_all, int32_t *flag_all, int32_t *la_all, int32_t *lb_all,
     int32_t *lc_all, double *hist_all, rd_result *__restrict__ out) {
-  __shared__ double red[PUSH_WAVES];
+  __shared__ long long red[2 * PUSH_WAVES];
   __shared__ int32_t cnt_c, cnt_next;
   const size_t off = (size_t)blockIdx.x * n;
   double *vcur = va_all + off, *vprev = vb_all + off, *y = y_all + off;
@@ -76,44 +109,33 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(
         hist[2 * k + i] = v1s * vcur[s] + v1t * vcur[t];
       }
       __syncthreads();
-      // push: a thread per frontier node with at most 64 entries, a wavefront
-      // (lanes over the entries) per longer row
+      // targets: every neighbour v that receives a push (|v_i(u)| >
+      // eps sqrt(d_u d_v)) joins the candidates; a thread per frontier node with
+      // at most 64 entries, a wavefront (lanes over the entries) per longer row
       for (int32_t idx = threadIdx.x; idx < nf; idx += PUSH_THREADS) {
         const int32_t u = fcur[idx];
         const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
         if (pe - pb > 64) continue;
-        const double val = vcur[u], su = sqrt(deg[u]);
+        const double val = fabs(vcur[u]), su = sqrt(deg[u]);
         for (int32_t p = pb; p < pe; ++p) {
           const int32_t v = col[p];
-          const double sq = su * sqrt(deg[v]);
-          if (fabs(val) > eps * sq) {
-            atomicAdd(&y[v], (WEIGHTED ? w[p] : 1.0) * val / sq);
-            if (atomicExch(&flag[v], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = v;
-          }
+          if (val > eps * (su * sqrt(deg[v])) && atomicExch(&flag[v], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = v;
         }
       }
       for (int32_t idx = wid; idx < nf; idx += PUSH_WAVES) {
         const int32_t u = fcur[idx];
         const int32_t pb = row_ptr[u], pe = row_ptr[u + 1];
         if (pe - pb <= 64) continue;
-        const double val = vcur[u], su = sqrt(deg[u]);
+        const double val = fabs(vcur[u]), su = sqrt(deg[u]);
         for (int32_t p = pb + lane; p < pe; p += 64) {
           const int32_t v = col[p];
-          const double sq = su * sqrt(deg[v]);
-          if (fabs(val) > eps * sq) {
-            atomicAdd(&y[v], (WEIGHTED ? w[p] : 1.0) * val / sq);
-            if (atomicExch(&flag[v], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = v;
-          }
+          if (val > eps * (su * sqrt(deg[v])) && atomicExch(&flag[v], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = v;
         }
       }
-      __syncthreads();
       // restrict: beta_i v_{i-1} on S_{i-1}; S_{i-1} and S_i join the candidates
       for (int32_t idx = threadIdx.x; idx < nfp; idx += PUSH_THREADS) {
         const int32_t u = fprev[idx];
-        if (fabs(vprev[u]) > eps * deg[u]) {
-          y[u] -= beta * vprev[u];
-          if (atomicExch(&flag[u], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = u;
-        }
+        if (fabs(vprev[u]) > eps * deg[u] && atomicExch(&flag[u], 1) == 0) cand[atomicAdd(&cnt_c, 1)] = u;
       }
       for (int32_t idx = threadIdx.x; idx < nf; idx += PUSH_THREADS) {
         const int32_t u = fcur[idx];
@@ -121,13 +143,28 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(
       }
       __syncthreads();
       const int32_t nc = cnt_c;
-      double a = 0.0;
+      // each candidate's sum, pulled in adjacency order (deterministic): AMV,
+      // then - beta_i v_{i-1} on S_{i-1}; alpha_i in fixed point
+      long long ah = 0, al = 0;
       for (int32_t idx = threadIdx.x; idx < nc; idx += PUSH_THREADS) {
         const int32_t v = cand[idx];
-        a += y[v] * vcur[v];
+        const double sv = sqrt(deg[v]);
+        double acc = 0.0;
+        const int32_t pe = row_ptr[v + 1];
+        for (int32_t p = row_ptr[v]; p < pe; ++p) {
+          const int32_t u = col[p];
+          const double val = vcur[u];
+          if (val == 0.0) continue;
+          const double sq = sqrt(deg[u]) * sv;
+          if (fabs(val) > eps * sq) acc += (WEIGHTED ? w[p] : 1.0) * val / sq;
+        }
+        const double vp = vprev[v];
+        if (fabs(vp) > eps * deg[v]) acc -= beta * vp;
+        y[v] = acc;
+        fx_add(acc * vcur[v], ah, al);
       }
-      const double alpha = block_sum(a, red);
-      double b2 = 0.0;
+      const double alpha = fx_block_total(ah, al, red);
+      long long bh = 0, bl = 0;
       for (int32_t idx = threadIdx.x; idx < nc; idx += PUSH_THREADS) {
         const int32_t v = cand[idx];
         double x = y[v];
@@ -135,9 +172,9 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(
           x -= alpha * vcur[v];
           y[v] = x;
         }
-        b2 += x * x;
+        fx_add(x * x, bh, bl);
       }
-      const double bnext = sqrt(block_sum(b2, red));
+      const double bnext = sqrt(fx_block_total(bh, bl, red));
       if (threadIdx.x == 0) {
         hist[i] = alpha;
         hist[k + i] = bnext;
