@@ -324,15 +324,17 @@ rd_status rd_power_method(rd_graph g, int32_t npairs, const int32_t *s, const in
  * removes the mean, so phi_p sums to zero as L^+ b does. The flow of edge
  * e = (u, v) is f(e) = w_e (phi_p(u) - phi_p(v)). phi is double[npairs * n],
  * row p holding phi_p in the caller's node order. out (may be NULL) receives
- * r as the FP64 energy 2 b^T phi - phi^T L phi (as with refine = 1). The runs
- * go in groups of block_width pairs (0: the width rd_tune_width picks) with
- * the stopping rule of rd_query_batch on r; the error of phi is of the order
- * of the square root of r's (r's error is second order in phi's). Options as
- * for rd_query_batch (refine is implied). When o->flags has RD_DEVICE_PTRS,
- * s, t, out and phi are device pointers. Errors as for rd_query_batch;
- * phi == NULL is RD_E_ARG. Device memory: that of rd_query_batch's
- * refinement mode (two more n x width blocks), plus npairs * n doubles for phi
- * when it is host memory.
+ * the r_hat of each run as rd_query_batch gives it. The pairs run with refill
+ * on block_width columns (0: the width rd_tune_width picks) and the stopping
+ * rule of rd_query_batch; each finished potential moves to a slot of a block
+ * of the same width, which is copied out when full (and once at the end).
+ * The error of phi is of the order of the square root of r's (r's error is
+ * second order in phi's). Options as for rd_query_batch (refine is ignored).
+ * When o->flags has RD_DEVICE_PTRS, s, t, out and phi are device pointers.
+ * Errors as for rd_query_batch; phi == NULL is RD_E_ARG. Device memory: three
+ * more n x width blocks than rd_query_batch (search directions, potentials,
+ * finished potentials), plus npairs * n doubles for phi when it is host
+ * memory.
  */
 rd_status rd_potentials(rd_graph g, int32_t npairs, const int32_t *s, const int32_t *t, double eps,
                         const rd_options *o, rd_result *out, double *phi);

@@ -410,6 +410,8 @@ struct RunParams {
   const double *grad_r;   // harvest mode: weight of each pair (nullptr: ones)
   int32_t s2;             // sparse second iterations on
   int64_t s2_ecap;        // at most this many scatter entries per column
+  int32_t *slot_pair = nullptr;  // harvest mode for potentials: pair of each slot
+  double *phi = nullptr;         // and the potentials' destination [npairs][n]
 };
 
 __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
@@ -515,7 +517,10 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       // run's scale for its last term; k_first_batch sets the new one)
       const bool final_term = fin && advanced && S.status != LZ_BREAKDOWN;
       const int32_t sl = slot[j];
-      if (sl >= 0) cw[sl] = (grad_r ? grad_r[S.pair] : 1.0) * S.c;
+      if (sl >= 0) {
+        cw[sl] = (grad_r ? grad_r[S.pair] : 1.0) * S.c;
+        if (prm.slot_pair) prm.slot_pair[sl] = S.pair;
+      }
       cc.hslot = sl;
       cc.pa = pa;
       cc.xb = xb;
@@ -917,10 +922,14 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_grad_edges(
 // After the edge pass of a full harvest block: the slots are free again and
 // their weights zero (so a final pass over a partly filled block counts only
 // the slots in use).
-__global__ void k_harvest_reset(int32_t B, int32_t *__restrict__ qstate, double *__restrict__ cw) {
+__global__ void k_harvest_reset(int32_t B, int32_t *__restrict__ qstate, double *__restrict__ cw,
+                                int32_t *__restrict__ slot_pair) {
   if (qstate[4] != B) return;
   __syncthreads();
-  for (int j = threadIdx.x; j < B; j += blockDim.x) cw[j] = 0.0;
+  for (int j = threadIdx.x; j < B; j += blockDim.x) {
+    cw[j] = 0.0;
+    if (slot_pair) slot_pair[j] = -1;
+  }
   __syncthreads();
   if (threadIdx.x == 0) qstate[4] = 0;
 }
@@ -990,7 +999,9 @@ __global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restric
 // Per-column partial sums of X over the rows (fixed order, as the products).
 template <typename VT, int B>
 __global__ __launch_bounds__(SHORT_THREADS) void k_col_reduce(int32_t n, const VT *__restrict__ X,
-                                                            double *__restrict__ part, int32_t ldp) {
+                                                            double *__restrict__ part, int32_t ldp,
+                                                            const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   __shared__ double sm[(SHORT_THREADS / 64) * B];
@@ -1009,21 +1020,28 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_col_reduce(int32_t n, const V
   block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
 }
 
-// phi_p = Pi sqrt(c_p) X[:, j] in the caller's node order (perm: caller id ->
-// row; nullptr: the identity), one row of n values per pair; colsum[j] is the
-// column's sum, so the mean is removed (phi sums to zero, as L^+ b does).
+// 1 when the block of harvested potentials is full (qstate[4] == B), else 0.
+__global__ void k_full_flag(int32_t B, const int32_t *__restrict__ qstate, int32_t *__restrict__ flag) {
+  if (threadIdx.x == 0) *flag = qstate[4] == B ? 1 : 0;
+}
+
+// phi_p = Pi sqrt(c_p) Xf[:, j] for the pair p held by harvest slot j, in the
+// caller's node order (perm: caller id -> row; nullptr: the identity), one row
+// of n values per pair; colsum[j] is the column's sum, so the mean is removed
+// (phi sums to zero, as L^+ b does); cw[j] = c_p (the pairs' weights are ones).
 template <typename VT, int B>
-__global__ void k_pot_out(int32_t n, const int32_t *__restrict__ perm, const LzState *__restrict__ st,
-                          const VT *__restrict__ X, const double *__restrict__ colsum,
-                          double *__restrict__ phi) {
+__global__ void k_pot_out(int32_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ slot_pair,
+                          const double *__restrict__ cw, const VT *__restrict__ X,
+                          const double *__restrict__ colsum, double *__restrict__ phi,
+                          const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (u >= n) return;
-  const LzState &S = st[j];
-  if (S.pair < 0) return;
-  const double sc = sqrt(S.c);
+  const int32_t pair = slot_pair[j];
+  if (pair < 0) return;
   const int32_t r = perm ? perm[u] : u;
-  phi[(size_t)S.pair * n + u] = sc * ((double)X[(size_t)r * B + j] - colsum[j] / n);
+  phi[(size_t)pair * n + u] = sqrt(cw[j]) * ((double)X[(size_t)r * B + j] - colsum[j] / n);
 }
 
 // grad_w in caller edge order from the adjacency-order accumulator (one
@@ -1738,6 +1756,13 @@ struct BatchWork {
   size_t pot_bytes = 0;
   double *gacc = nullptr;  // [nnz]: edge gradient by adjacency entry (upper entries used)
   double *cw = nullptr;    // [256]
+  // potentials harvest mode: column partials and sums of the block, the pair
+  // of each slot, the full-block flag
+  double *ppart = nullptr;  // [256][grid_upd]
+  double *psum = nullptr;   // [256]
+  int32_t *spair = nullptr; // [256]
+  int32_t *pflag = nullptr;
+  int32_t ppart_ld = 0;
   LzState *st = nullptr;
   ColCtrl *ctrl = nullptr;
   int32_t *qstate = nullptr;       // [8]: queue head, active columns, working iterations, 1,
@@ -1777,6 +1802,10 @@ void batch_free(rd_graph g) {
   dev_free(bw->Xf);
   dev_free(bw->gacc);
   dev_free(bw->cw);
+  dev_free(bw->ppart);
+  dev_free(bw->psum);
+  dev_free(bw->spair);
+  dev_free(bw->pflag);
   dev_free(bw->st);
   dev_free(bw->ctrl);
   dev_free(bw->qstate);
@@ -2065,6 +2094,26 @@ bool sparse_second_single(rd_graph g, int32_t precision, void *U1, void *U2, LzS
   return true;
 }
 
+// The potentials of the harvest block: column sums, then the copy-out of the
+// slots in use. gated: only when the block is full (the flag is set first);
+// otherwise active is the constant 1 (the last, partly filled block).
+template <typename VT, int B>
+static void launch_pot_out(rd_graph g, BatchWork *bw, const RunParams &prm, const int32_t *flag, bool gated,
+                           hipStream_t st) {
+  const int32_t *active = bw->qstate + 3;
+  if (gated) {
+    hipLaunchKernelGGL(k_full_flag, dim3(1), dim3(64), 0, st, B, (const int32_t *)bw->qstate, bw->pflag);
+    active = flag;
+  }
+  hipLaunchKernelGGL((k_col_reduce<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                     (const VT *)bw->Xf, bw->ppart, bw->ppart_ld, active);
+  hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart, bw->ppart_ld,
+                     bw->grid_upd, bw->psum, active);
+  hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
+                     (const int32_t *)g->perm, (const int32_t *)prm.slot_pair, (const double *)bw->cw,
+                     (const VT *)bw->Xf, (const double *)bw->psum, prm.phi, active);
+}
+
 // The three vector blocks of a run: q_{i-1}, q_i and the block the next
 // product writes (they rotate every iteration).
 struct RunBufs {
@@ -2110,11 +2159,15 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
                        g->deg, Ucur, Uprev, Y, bw->ctrl, bw->part, bw->ldp, active, (VT *)bw->P,
                        (VT *)bw->Xp, 0, bw->rpart, (VT *)bw->Xf);
   if (prm.gmode == GRAD_HARVEST) {
-    // a full block of harvested potentials: its edge pass, then the slots are free
-    hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
-                       (const int4 *)g->echunk, g->col, (const VT *)bw->Xf, (const double *)bw->cw, bw->gacc,
-                       (const int32_t *)(bw->qstate + 4));
-    hipLaunchKernelGGL(k_harvest_reset, dim3(1), dim3(256), 0, st, B, bw->qstate, bw->cw);
+    // a full block of harvested potentials: its edge pass (or, for potentials,
+    // its copy-out), then the slots are free
+    if (prm.slot_pair)
+      launch_pot_out<VT, B>(g, bw, prm, bw->pflag, true, st);
+    else
+      hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                         (const int4 *)g->echunk, g->col, (const VT *)bw->Xf, (const double *)bw->cw, bw->gacc,
+                         (const int32_t *)(bw->qstate + 4));
+    hipLaunchKernelGGL(k_harvest_reset, dim3(1), dim3(256), 0, st, B, bw->qstate, bw->cw, prm.slot_pair);
   }
   if (prm.reorth > 0) {
     // column sums of the three coefficient slabs (rpart holds [3][B][ldp])
@@ -2305,7 +2358,8 @@ template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
                        rd_result *out, float *grad_w, hipStream_t st, bool prof, double *phi = nullptr) {
-  const bool refine = grad_w == nullptr;
+  const bool pots = phi != nullptr;  // potentials: harvest mode with a copy-out per block
+  const bool refine = grad_w == nullptr && !pots;
   batch_reserve(g, bw, B, sizeof(VT));
   const size_t need = (size_t)g->n * B * sizeof(VT);  // potentials stored like the vectors
   if (need > bw->pot_bytes) {
@@ -2319,11 +2373,20 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     bw->pot_bytes = need;
   }
   if (!refine && !bw->Xf) bw->Xf = dev_alloc(bw->pot_bytes);
-  if (!refine && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->nnz * sizeof(double));
+  if (!refine && !pots && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->nnz * sizeof(double));
+  if (pots && (!bw->ppart || bw->ppart_ld < bw->grid_upd)) {
+    dev_free(bw->ppart);
+    bw->ppart = nullptr;
+    bw->ppart = (double *)dev_alloc((size_t)256 * bw->grid_upd * sizeof(double));
+    bw->ppart_ld = bw->grid_upd;
+  }
+  if (pots && !bw->psum) bw->psum = (double *)dev_alloc(256 * sizeof(double));
+  if (pots && !bw->spair) bw->spair = (int32_t *)dev_alloc(256 * sizeof(int32_t));
+  if (pots && !bw->pflag) bw->pflag = (int32_t *)dev_alloc(sizeof(int32_t));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
   edge_chunks(g, st);
   if (!refine) {
-    RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->nnz * sizeof(double), st));
+    if (!pots) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->nnz * sizeof(double), st));
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xf, 0, need, st));
@@ -2331,7 +2394,18 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     RunParams prm = prm0;
     prm.gmode = GRAD_HARVEST;
     prm.grad_r = grad_r;
+    if (pots) {
+      RD_HIP(hipMemsetAsync(bw->spair, 0xff, 256 * sizeof(int32_t), st));  // -1: no pair
+      prm.slot_pair = bw->spair;
+      prm.phi = phi;
+    }
     if (npairs > 0) batch_run_t<VT, B, true>(g, bw, npairs, ps, pt, prm, out, st, prof);
+    if (pots) {
+      // the last, partly filled block (unused slots hold no pair)
+      launch_pot_out<VT, B>(g, bw, prm, nullptr, false, st);
+      RD_HIP(hipGetLastError());
+      return;
+    }
     // the last, partly filled harvest block (unused slots have weight zero)
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (prof) {
@@ -2374,16 +2448,6 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
                        bw->cw, bw->qstate + 3);
     hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
                        (const VT *)bw->Xp, (const double *)bw->cw, out + off);
-    if (phi) {
-      // the group's potentials, mean removed, in the caller's node order
-      hipLaunchKernelGGL((k_col_reduce<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                         (const VT *)bw->Xp, bw->part, bw->ldp);
-      hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
-                         bw->cw, bw->qstate + 3);
-      hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
-                         (const int32_t *)g->perm, (const LzState *)bw->st, (const VT *)bw->Xp,
-                         (const double *)bw->cw, phi + (size_t)off * g->n);
-    }
     RD_HIP(hipGetLastError());
   }
 }
