@@ -307,8 +307,8 @@ def run_other(name, args):
                 k += 1
         line = _line("pairs/s (potentials)", len(s) / pdt, steps, 1, pdt * 1e3, "f32",
                      {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "eps_rel": eps,
-                      "path": "rd_potentials, FP32 vectors, width 64, groups of 64 pairs, phi (FP64, 256 x n) "
-                              "left in device memory",
+                      "path": "rd_potentials, FP32 vectors, width 64, harvest mode with refill, phi (FP64, "
+                              "256 x n) left in device memory",
                       "node_order": "decreasing degree (RD_REORDER)"},
                      roofline={"kernel": "k_spmm_short (batched FP32 sparse product over the short rows)",
                                "bound": "hbm", "achieved": round(b / (avg * 1e-3) / 1e9, 1) if nl else None,
