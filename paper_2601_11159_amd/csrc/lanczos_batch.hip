@@ -63,7 +63,7 @@ __device__ __forceinline__ bool starts_pair(int32_t mode) {
 }
 
 // gradient handling of a batched run
-enum : int32_t { GRAD_NONE = 0, GRAD_GROUPS = 1, GRAD_HARVEST = 2 };
+enum : int32_t { GRAD_NONE = 0, GRAD_HARVEST = 2 };
 
 struct ColCtrl {
   double sig;   // q = sig * U_cur[:, j]
@@ -406,12 +406,13 @@ struct RunParams {
   int32_t max_iters, fixed_k, delay, err_mode;
   int32_t npairs;
   int32_t reorth;
-  int32_t gmode;          // GRAD_NONE, GRAD_GROUPS or GRAD_HARVEST
+  int32_t gmode;          // GRAD_NONE or GRAD_HARVEST
   const double *grad_r;   // harvest mode: weight of each pair (nullptr: ones)
   int32_t s2;             // sparse second iterations on
   int64_t s2_ecap;        // at most this many scatter entries per column
-  int32_t *slot_pair = nullptr;  // harvest mode for potentials: pair of each slot
-  double *phi = nullptr;         // and the potentials' destination [npairs][n]
+  int32_t *slot_pair = nullptr;  // harvest mode for potentials and energies: pair of each slot
+  double *phi = nullptr;         // the potentials' destination [npairs][n], or nullptr
+  int32_t refine = 0;            // 1: r of each pair as the FP64 energy of its potential
 };
 
 __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
@@ -426,8 +427,7 @@ __device__ __forceinline__ void write_result(rd_result *out, const LzState &S) {
 // Scalar step for every column after alpha, then retirement and refill in
 // column order (one block; thread 0 pops the pair queue and hands out harvest
 // slots serially, so the assignment of pairs and slots is deterministic).
-// grad: GRAD_NONE, GRAD_GROUPS (no refill; a stopped run adds its last
-// potential term, then idles) or GRAD_HARVEST (a stopped run adds its last
+// grad: GRAD_NONE or GRAD_HARVEST (a stopped run adds its last
 // term and its potential is copied to a harvest slot, with weight
 // cw[slot] = grad_r[pair] * c, before the column is refilled).
 __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict__ st,
@@ -561,19 +561,17 @@ __global__ __launch_bounds__(256) void k_control(int32_t B, LzState *__restrict_
       cc.t = t;
       active = 1;
     } else if (np == -1) {
-      // a run that stopped at this iteration still adds its last term to the
-      // potential (gradient groups); the column is idle afterwards
-      const bool final_term = grad == GRAD_GROUPS && advanced && S.status != LZ_BREAKDOWN;
+      // no pair left (without harvest: the finished potential is not kept);
+      // the column is idle afterwards
       S.status = LZ_IDLE;
-      cc.mode = final_term ? COL_FINAL : COL_IDLE;
+      cc.mode = COL_IDLE;
       cc.hslot = -1;
       cc.pa = pa;
       cc.xb = xb;
-      if (final_term) active = 1;
       cc.pc = 0.0;
       cc.coef = 0.0;
       cc.upd_sparse = 0;
-      if (!final_term) cc.sig = 0.0;
+      cc.sig = 0.0;
     } else {
       cc.mode = COL_RUN;
       cc.coef = S.alpha * S.sig_cur;
@@ -940,7 +938,8 @@ template <typename PT, int B, bool WEIGHTED>
 __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
     int32_t nch, const int4 *__restrict__ chunk, const int32_t *__restrict__ col,
     const double *__restrict__ w64, const PT *__restrict__ X, double *__restrict__ part,
-    int32_t ldp) {
+    int32_t ldp, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   using S = Shape<B>;
   constexpr int VEC = S::VEC;
   using XV = VecN<double, VEC>;
@@ -984,16 +983,22 @@ __global__ __launch_bounds__(SHORT_THREADS) void k_energy(
   block_column_partials<B, VEC>(acc, sm, part, ldp, blockIdx.x);
 }
 
-// r = J(phi) = 2 (phi_s - phi_t) - phi^T L phi with phi = sqrt(c) X[:, j] (FP64).
+// r = J(phi) = 2 (phi_s - phi_t) - phi^T L phi with phi = sqrt(c) Xf[:, j] (FP64)
+// for the pair p held by harvest slot j (cw[j] = c_p; energy[j] = the column's
+// sum_e w_e (Xf[u, j] - Xf[v, j])^2).
 template <typename VT, int B>
-__global__ void k_refine_out(const LzState *__restrict__ st, const VT *__restrict__ X,
-                             const double *__restrict__ energy, rd_result *__restrict__ out) {
+__global__ void k_refine_out(const int32_t *__restrict__ slot_pair, const int32_t *__restrict__ ps,
+                             const int32_t *__restrict__ pt, const double *__restrict__ cw,
+                             const VT *__restrict__ X, const double *__restrict__ energy,
+                             rd_result *__restrict__ out, const int32_t *__restrict__ active) {
+  if (*active == 0) return;
   const int j = threadIdx.x;
   if (j >= B) return;
-  const LzState &S = st[j];
-  if (S.pair < 0) return;
-  const double xs = (double)X[(size_t)S.s * B + j], xt = (double)X[(size_t)S.t * B + j];
-  out[S.pair].r = 2.0 * sqrt(S.c) * (xs - xt) - S.c * energy[j];
+  const int32_t pair = slot_pair[j];
+  if (pair < 0) return;
+  const double c = cw[j];
+  const double xs = (double)X[(size_t)ps[pair] * B + j], xt = (double)X[(size_t)pt[pair] * B + j];
+  out[pair].r = 2.0 * sqrt(c) * (xs - xt) - c * energy[j];
 }
 
 // Per-column partial sums of X over the rows (fixed order, as the products).
@@ -2094,24 +2099,42 @@ bool sparse_second_single(rd_graph g, int32_t precision, void *U1, void *U2, LzS
   return true;
 }
 
-// The potentials of the harvest block: column sums, then the copy-out of the
-// slots in use. gated: only when the block is full (the flag is set first);
-// otherwise active is the constant 1 (the last, partly filled block).
+// What a full block of harvested potentials gives besides the edge gradient:
+// the potentials themselves (column sums, then the copy-out of the slots in
+// use) and/or the FP64 energy of each one (r rewritten as J(phi)). gated: only
+// when the block is full (the flag is set first); otherwise active is the
+// constant 1 (the last, partly filled block).
 template <typename VT, int B>
-static void launch_pot_out(rd_graph g, BatchWork *bw, const RunParams &prm, const int32_t *flag, bool gated,
-                           hipStream_t st) {
+static void launch_block_out(rd_graph g, BatchWork *bw, const RunParams &prm, const int32_t *ps,
+                             const int32_t *pt, rd_result *out, bool gated, hipStream_t st) {
   const int32_t *active = bw->qstate + 3;
   if (gated) {
     hipLaunchKernelGGL(k_full_flag, dim3(1), dim3(64), 0, st, B, (const int32_t *)bw->qstate, bw->pflag);
-    active = flag;
+    active = bw->pflag;
   }
-  hipLaunchKernelGGL((k_col_reduce<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
-                     (const VT *)bw->Xf, bw->ppart, bw->ppart_ld, active);
-  hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart, bw->ppart_ld,
-                     bw->grid_upd, bw->psum, active);
-  hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
-                     (const int32_t *)g->perm, (const int32_t *)prm.slot_pair, (const double *)bw->cw,
-                     (const VT *)bw->Xf, (const double *)bw->psum, prm.phi, active);
+  if (prm.phi) {
+    hipLaunchKernelGGL((k_col_reduce<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->n,
+                       (const VT *)bw->Xf, bw->ppart, bw->ppart_ld, active);
+    hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart,
+                       bw->ppart_ld, bw->grid_upd, bw->psum, active);
+    hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
+                       (const int32_t *)g->perm, (const int32_t *)prm.slot_pair, (const double *)bw->cw,
+                       (const VT *)bw->Xf, (const double *)bw->psum, prm.phi, active);
+  }
+  if (prm.refine) {
+    if (g->unit)
+      hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                         (const int4 *)g->echunk, g->col, (const double *)nullptr, (const VT *)bw->Xf,
+                         bw->ppart, bw->ppart_ld, active);
+    else
+      hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
+                         (const int4 *)g->echunk, g->col, (const double *)g->w64, (const VT *)bw->Xf,
+                         bw->ppart, bw->ppart_ld, active);
+    hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart,
+                       bw->ppart_ld, bw->grid_upd, bw->psum, active);
+    hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const int32_t *)prm.slot_pair, ps, pt,
+                       (const double *)bw->cw, (const VT *)bw->Xf, (const double *)bw->psum, out, active);
+  }
 }
 
 // The three vector blocks of a run: q_{i-1}, q_i and the block the next
@@ -2162,7 +2185,7 @@ static void enqueue_batch_iteration(rd_graph g, BatchWork *bw, const RunBufs &rb
     // a full block of harvested potentials: its edge pass (or, for potentials,
     // its copy-out), then the slots are free
     if (prm.slot_pair)
-      launch_pot_out<VT, B>(g, bw, prm, bw->pflag, true, st);
+      launch_block_out<VT, B>(g, bw, prm, ps, pt, out, true, st);
     else
       hipLaunchKernelGGL((k_grad_edges<VT, B>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st, g->nch,
                          (const int4 *)g->echunk, g->col, (const VT *)bw->Xf, (const double *)bw->cw, bw->gacc,
@@ -2351,15 +2374,19 @@ static int64_t batch_dispatch(rd_graph g, BatchWork *bw, int32_t B, int32_t npai
 // the column is refilled; every full block of B harvested potentials gets one
 // edge pass into the FP64 accumulator, and the last, partly filled block one
 // more at the end.
-// grad_w == nullptr: refinement mode - pairs in groups of B (one run per
-// group, no refill), then each group's results get r = J(phi), the FP64
-// energy of its potentials.
+// grad_w == nullptr, phi != nullptr: the same run; each block's potentials are
+// copied out (mean removed, caller's node order) instead of the edge pass.
+// grad_w == nullptr, phi == nullptr: refinement; each block's potentials give
+// their pairs r = J(phi), the FP64 energy, in place of r_hat.
 template <typename VT, int B>
 static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t *ps,
                        const int32_t *pt, const double *grad_r, const RunParams &prm0,
                        rd_result *out, float *grad_w, hipStream_t st, bool prof, double *phi = nullptr) {
-  const bool pots = phi != nullptr;  // potentials: harvest mode with a copy-out per block
+  // all three modes run with refill and harvest finished potentials into
+  // blocks: the edge gradient, the potentials' copy-out, or the energies (refine)
+  const bool pots = phi != nullptr;
   const bool refine = grad_w == nullptr && !pots;
+  const bool grad = grad_w != nullptr;
   batch_reserve(g, bw, B, sizeof(VT));
   const size_t need = (size_t)g->n * B * sizeof(VT);  // potentials stored like the vectors
   if (need > bw->pot_bytes) {
@@ -2372,21 +2399,21 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     bw->Xp = dev_alloc(need);
     bw->pot_bytes = need;
   }
-  if (!refine && !bw->Xf) bw->Xf = dev_alloc(bw->pot_bytes);
-  if (!refine && !pots && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->nnz * sizeof(double));
-  if (pots && (!bw->ppart || bw->ppart_ld < bw->grid_upd)) {
+  if (!bw->Xf) bw->Xf = dev_alloc(bw->pot_bytes);
+  if (grad && !bw->gacc) bw->gacc = (double *)dev_alloc((size_t)g->nnz * sizeof(double));
+  if (!grad && (!bw->ppart || bw->ppart_ld < bw->grid_upd)) {
     dev_free(bw->ppart);
     bw->ppart = nullptr;
     bw->ppart = (double *)dev_alloc((size_t)256 * bw->grid_upd * sizeof(double));
     bw->ppart_ld = bw->grid_upd;
   }
-  if (pots && !bw->psum) bw->psum = (double *)dev_alloc(256 * sizeof(double));
-  if (pots && !bw->spair) bw->spair = (int32_t *)dev_alloc(256 * sizeof(int32_t));
-  if (pots && !bw->pflag) bw->pflag = (int32_t *)dev_alloc(sizeof(int32_t));
+  if (!grad && !bw->psum) bw->psum = (double *)dev_alloc(256 * sizeof(double));
+  if (!grad && !bw->spair) bw->spair = (int32_t *)dev_alloc(256 * sizeof(int32_t));
+  if (!grad && !bw->pflag) bw->pflag = (int32_t *)dev_alloc(sizeof(int32_t));
   if (!bw->cw) bw->cw = (double *)dev_alloc(256 * sizeof(double));
   edge_chunks(g, st);
-  if (!refine) {
-    if (!pots) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->nnz * sizeof(double), st));
+  {
+    if (grad) RD_HIP(hipMemsetAsync(bw->gacc, 0, (size_t)g->nnz * sizeof(double), st));
     RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
     RD_HIP(hipMemsetAsync(bw->Xf, 0, need, st));
@@ -2394,15 +2421,16 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
     RunParams prm = prm0;
     prm.gmode = GRAD_HARVEST;
     prm.grad_r = grad_r;
-    if (pots) {
+    if (!grad) {
       RD_HIP(hipMemsetAsync(bw->spair, 0xff, 256 * sizeof(int32_t), st));  // -1: no pair
       prm.slot_pair = bw->spair;
       prm.phi = phi;
+      prm.refine = refine ? 1 : 0;
     }
     if (npairs > 0) batch_run_t<VT, B, true>(g, bw, npairs, ps, pt, prm, out, st, prof);
-    if (pots) {
+    if (!grad) {
       // the last, partly filled block (unused slots hold no pair)
-      launch_pot_out<VT, B>(g, bw, prm, nullptr, false, st);
+      launch_block_out<VT, B>(g, bw, prm, ps, pt, out, false, st);
       RD_HIP(hipGetLastError());
       return;
     }
@@ -2427,28 +2455,6 @@ static void grad_run_t(rd_graph g, BatchWork *bw, int32_t npairs, const int32_t 
       g->timer[2].resolve(g->timer[2].used);
     }
     return;
-  }
-  for (int32_t off = 0; off < npairs; off += B) {
-    const int32_t nb = std::min<int32_t>(B, npairs - off);
-    RD_HIP(hipMemsetAsync(bw->P, 0, need, st));
-    RD_HIP(hipMemsetAsync(bw->Xp, 0, need, st));
-    RunParams prm = prm0;
-    prm.npairs = nb;
-    prm.gmode = GRAD_GROUPS;
-    batch_run_t<VT, B, true>(g, bw, nb, ps + off, pt + off, prm, out + off, st, prof);
-    if (g->unit)
-      hipLaunchKernelGGL((k_energy<VT, B, false>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                         g->nch, (const int4 *)g->echunk, g->col, (const double *)nullptr,
-                         (const VT *)bw->Xp, bw->part, bw->ldp);
-    else
-      hipLaunchKernelGGL((k_energy<VT, B, true>), dim3(bw->grid_upd), dim3(SHORT_THREADS), 0, st,
-                         g->nch, (const int4 *)g->echunk, g->col, (const double *)g->w64,
-                         (const VT *)bw->Xp, bw->part, bw->ldp);
-    hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, bw->part, bw->ldp, bw->grid_upd,
-                       bw->cw, bw->qstate + 3);
-    hipLaunchKernelGGL((k_refine_out<VT, B>), dim3(1), dim3(256), 0, st, (const LzState *)bw->st,
-                       (const VT *)bw->Xp, (const double *)bw->cw, out + off);
-    RD_HIP(hipGetLastError());
   }
 }
 
@@ -2759,7 +2765,7 @@ rd_status rd_query_batch(rd_graph g, int32_t npairs, const int32_t *s, const int
                   GRAD_NONE, nullptr,       (opt.flags & RD_NO_SPARSE2) ? 0 : 1, 0};
     const bool prof = opt.flags & RD_PROFILE;
     if (opt.refine) {
-      // groups of B pairs with potentials, r reported as the FP64 energy
+      // runs with potentials (harvested per block), r reported as the FP64 energy
       if (opt.precision == RD_F64)
         grad_dispatch<double>(g, bw, B, npairs, ds, dt, nullptr, prm, dout, nullptr, st, prof);
       else
@@ -2906,7 +2912,7 @@ rd_status rd_potentials(rd_graph g, int32_t npairs, const int32_t *s, const int3
                "block_width must be 0 or one of 16, 32, 64, 128, 256");
     if (B == 0) B = autotune_width(g, bw, opt.precision, npairs, st);
     RD_HIP(hipMemsetAsync(dphi, 0, phi_bytes, st));
-    // groups of B pairs with potentials (the refinement mode), r as the FP64 energy
+    // runs with potentials, harvested per block and copied out
     RunParams prm{eps,       opt.max_iters, opt.fixed_k, opt.delay, opt.err_mode, npairs, opt.reorth,
                   GRAD_NONE, nullptr,       (opt.flags & RD_NO_SPARSE2) ? 0 : 1, 0};
     const bool prof = opt.flags & RD_PROFILE;
