@@ -110,7 +110,9 @@ typedef struct {
                           of Algorithm 5) instead of r_hat. J <= r, and r - J equals
                           the squared energy-norm error of phi, so rounding in
                           FP32 vectors enters only to second order. Pairs run
-                          in groups of block_width without refill. */
+                          with refill; finished potentials are harvested into
+                          blocks of block_width whose energies are taken per
+                          block. */
   int32_t reorth;      /* re-orthogonalisation of w after w -= alpha_i v_i
                           (not in Algorithm 3, which relies on v_1 being
                           exactly orthogonal to u_1 = D^{1/2} 1 / sqrt(vol),
