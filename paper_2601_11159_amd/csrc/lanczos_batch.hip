@@ -1040,13 +1040,17 @@ __global__ void k_pot_out(int32_t n, const int32_t *__restrict__ perm, const int
                           const double *__restrict__ colsum, double *__restrict__ phi,
                           const int32_t *__restrict__ active) {
   if (*active == 0) return;
-  const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (u >= n) return;
-  const int32_t pair = slot_pair[j];
-  if (pair < 0) return;
-  const int32_t r = perm ? perm[u] : u;
-  phi[(size_t)pair * n + u] = sqrt(cw[j]) * ((double)X[(size_t)r * B + j] - colsum[j] / n);
+  // grid-stride over (slot, node), node fastest: a gated-off launch is cheap
+  const int64_t total = (int64_t)n * B;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / n);
+    const int32_t u = (int32_t)(e - (int64_t)j * n);
+    const int32_t pair = slot_pair[j];
+    if (pair < 0) continue;
+    const int32_t r = perm ? perm[u] : u;
+    phi[(size_t)pair * n + u] = sqrt(cw[j]) * ((double)X[(size_t)r * B + j] - colsum[j] / n);
+  }
 }
 
 // grad_w in caller edge order from the adjacency-order accumulator (one
@@ -2117,7 +2121,8 @@ static void launch_block_out(rd_graph g, BatchWork *bw, const RunParams &prm, co
                        (const VT *)bw->Xf, bw->ppart, bw->ppart_ld, active);
     hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart,
                        bw->ppart_ld, bw->grid_upd, bw->psum, active);
-    hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(cdiv(g->n, 256), B), dim3(256), 0, st, g->n,
+    hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(std::min<int64_t>(cdiv((int64_t)g->n * B, 256), 4096)), dim3(256), 0,
+                       st, g->n,
                        (const int32_t *)g->perm, (const int32_t *)prm.slot_pair, (const double *)bw->cw,
                        (const VT *)bw->Xf, (const double *)bw->psum, prm.phi, active);
   }
