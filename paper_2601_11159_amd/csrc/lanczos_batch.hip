@@ -1035,21 +1035,38 @@ __global__ void k_full_flag(int32_t B, const int32_t *__restrict__ qstate, int32
 // of n values per pair; colsum[j] is the column's sum, so the mean is removed
 // (phi sums to zero, as L^+ b does); cw[j] = c_p (the pairs' weights are ones).
 template <typename VT, int B>
-__global__ void k_pot_out(int32_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ slot_pair,
-                          const double *__restrict__ cw, const VT *__restrict__ X,
-                          const double *__restrict__ colsum, double *__restrict__ phi,
-                          const int32_t *__restrict__ active) {
+__global__ __launch_bounds__(256) void k_pot_out(int32_t n, const int32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ slot_pair,
+                                                 const double *__restrict__ cw, const VT *__restrict__ X,
+                                                 const double *__restrict__ colsum, double *__restrict__ phi,
+                                                 const int32_t *__restrict__ active) {
   if (*active == 0) return;
-  // grid-stride over (slot, node), node fastest: a gated-off launch is cheap
-  const int64_t total = (int64_t)n * B;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e / n);
-    const int32_t u = (int32_t)(e - (int64_t)j * n);
-    const int32_t pair = slot_pair[j];
-    if (pair < 0) continue;
-    const int32_t r = perm ? perm[u] : u;
-    phi[(size_t)pair * n + u] = sqrt(cw[j]) * ((double)X[(size_t)r * B + j] - colsum[j] / n);
+  // tiles of 64 nodes x TJ slots through LDS: the block is read a row segment
+  // per node and phi written 64 consecutive nodes per slot (both coalesced);
+  // grid-stride over the tiles, so a gated-off launch is cheap
+  constexpr int TJ = B < 64 ? B : 64;
+  constexpr int JT = B / TJ;
+  __shared__ double tile[TJ][65];
+  const int32_t ntile = (int32_t)((n + 63) / 64) * JT;
+  for (int32_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int32_t u0 = (t / JT) * 64;
+    const int j0 = (t % JT) * TJ;
+    for (int e = threadIdx.x; e < 64 * TJ; e += 256) {
+      const int jj = e % TJ, uu = e / TJ;
+      const int32_t u = u0 + uu;
+      double x = 0.0;
+      if (u < n) x = (double)X[(size_t)(perm ? perm[u] : u) * B + j0 + jj];
+      tile[jj][uu] = x;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * TJ; e += 256) {
+      const int uu = e % 64, jj = e / 64;
+      const int32_t u = u0 + uu;
+      const int j = j0 + jj;
+      const int32_t pair = slot_pair[j];
+      if (u < n && pair >= 0) phi[(size_t)pair * n + u] = sqrt(cw[j]) * (tile[jj][uu] - colsum[j] / n);
+    }
+    __syncthreads();
   }
 }
 
@@ -2121,8 +2138,8 @@ static void launch_block_out(rd_graph g, BatchWork *bw, const RunParams &prm, co
                        (const VT *)bw->Xf, bw->ppart, bw->ppart_ld, active);
     hipLaunchKernelGGL(k_col_sum, dim3(B), dim3(COL_THREADS), 0, st, (const double *)bw->ppart,
                        bw->ppart_ld, bw->grid_upd, bw->psum, active);
-    hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(std::min<int64_t>(cdiv((int64_t)g->n * B, 256), 4096)), dim3(256), 0,
-                       st, g->n,
+    hipLaunchKernelGGL((k_pot_out<VT, B>), dim3(std::min<int64_t>(cdiv(g->n, 64) * (B < 64 ? 1 : B / 64), 4096)),
+                       dim3(256), 0, st, g->n,
                        (const int32_t *)g->perm, (const int32_t *)prm.slot_pair, (const double *)bw->cw,
                        (const VT *)bw->Xf, (const double *)bw->psum, prm.phi, active);
   }
