@@ -47,7 +47,7 @@ WORKLOADS = {
 OTHER_WORKLOADS = ["grid_64x64_100pairs_fp64", "chung_lu_n1M_g2.1_d20_plain_fp64",
                    "road_like_2000x2000_256pairs", "weighted_chung_lu_n1M_grad_256pairs",
                    "grid_64x64_100pairs_power_method", "weighted_chung_lu_n1M_potentials_256pairs",
-                   "condition_numbers", "road_like_2000x2000_lanczos_push"]
+                   "condition_numbers", "road_like_2000x2000_lanczos_push", "road_like_90x90_power_method"]
 
 
 def _line(metric_unit, value, steps, warmup, ms_per_step, dtype, config, **extra):
@@ -412,6 +412,75 @@ def run_other(name, args):
                                    "kind": "oracle", "sample": "one deflated numpy Algorithm 3 run with its Ritz values"},
                      parity={"grid_theta_max_abs_diff_vs_oracle": abs(c1["theta_max"] - float(th[-1])),
                              "grid_theta_min_abs_diff_vs_oracle": abs(c1["theta_min"] - float(th[0]))})
+    elif name == "road_like_90x90_power_method":
+        # the Power Method against Lanczos at equal error on a road-like graph
+        # (the paper's high-kappa case), at the configs' 1e-4 tolerance; 90 x 90
+        # so that both FP64 vectors fit in LDS (single-workgroup path)
+        g = I.road_like(90, seed=3)
+        s, t = I.uniform_pairs(g.n, 64, seed=3)
+        G = rd.RDGraph(g.n, g.u, g.v)
+        f64 = dict(precision=rd.RD_F64, block_width=64)
+        ref = G.query_batch(s, t, 1e-12, rd.rd_default_options(**f64))["r"]
+        target = 1e-4
+
+        def pm_err(l):
+            r = G.power_method(s, t, l, rd.rd_default_options(**f64))["r"]
+            e = float(np.max(np.abs(r - ref) / ref))
+            log(f"  l = {l}: max rel err {e:.3g}")
+            return e
+
+        hi = 8192
+        while pm_err(hi) > target and hi < (1 << 22):
+            hi *= 2
+        lo = hi // 2
+        while hi - lo > max(16, hi // 64):
+            mid = (lo + hi) // 2
+            if pm_err(mid) > target:
+                lo = mid
+            else:
+                hi = mid
+        l_pm = hi
+        log(f"  Power Method reaches {target:g} at l = {l_pm}")
+        opts = rd.rd_default_options(flags=rd.RD_PROFILE, **f64)
+        G.kernel_stats(0)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = G.power_method(s, t, l_pm, opts)
+        torch.cuda.synchronize()
+        pdt = time.time() - t0
+        ms, nl, b = G.kernel_stats(0)
+        avg = ms / max(nl, 1)
+        lz = G.query_batch(s, t, target, rd.rd_default_options(**f64))
+        bq, bout, broof, bdt = _batch_rate(G, rd, s, t, target, rd.rd_default_options(**f64), steps=2)
+        _, th, _ = G.ritz_bounds(int(s[0]), int(t[0]), 3000)
+        kappa = 2.0 / (1.0 - th)
+        from threadpoolctl import threadpool_limits
+        from oracle import power as PMO
+        P, d = PMO.transition_matrix(g)
+        with threadpool_limits(limits=1):
+            t1 = time.time()
+            v0 = PMO.power_method(g, int(s[0]), int(t[0]), l_pm, P=P, d=d)
+            osec = time.time() - t1
+        line = _line("queries/s", len(s) / pdt, 1, 1, pdt * 1e3, "f64",
+                     {"workload": name, "n": g.n, "m": g.m, "pairs": 64, "eps_rel": target,
+                      "path": f"rd_power_method, FP64, one workgroup per pair (k_pm_small), l = {l_pm} products per pair "
+                              f"(the least l, to within {max(16, l_pm // 64)}, whose results are all within "
+                              f"{target:g} of batched Lanczos at 1e-12)"},
+                     iterations={"power_method_l": l_pm, "lanczos_mean_k": float(lz["iters"].mean()),
+                                 "lanczos_max_k": int(lz["iters"].max()),
+                                 "ratio_l_over_k": round(l_pm / float(lz["iters"].mean()), 1),
+                                 "kappa_hat_k3000": round(kappa, 1), "sqrt_kappa_hat": round(float(np.sqrt(kappa)), 1)},
+                     lanczos_batched_fp64={"value": round(bq, 2), "unit": "queries/s",
+                                           "speedup_over_power_method": round(bq * pdt / len(s), 1)},
+                     roofline={"kernel": "k_pm_small (all steps of a pair in one workgroup, vectors in LDS)",
+                               "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                               "traffic": None, "avg_launch_ms": round(pdt * 1e3, 3), "launches": 1,
+                               "note": "LDS-resident: no HBM traffic per step; see the 64x64 grid line for "
+                                       "the batched-product roofline"},
+                     cpu_baseline={"value": round(1.0 / osec, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                                   "sample": "1 pair, numpy Algorithm 1 with the same l"},
+                     parity={"max_rel_err_vs_oracle": abs(float(out["r"][0]) - v0) / v0,
+                             "max_rel_err_vs_lanczos_1e-12": float(np.max(np.abs(out["r"] - ref) / ref))})
     elif name == "grid_64x64_100pairs_power_method":
         # the Power Method (Algorithm 1) against Lanczos at equal error (1e-8)
         import scipy.sparse as sps
