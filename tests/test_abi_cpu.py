@@ -102,3 +102,24 @@ def test_bench_traffic_lookup_hashes_the_kernel_source():
         workload, width = key.rsplit("/B", 1)
         got = bench.load_traffic(workload, int(width))
         assert (got is not None) == (e["source_hash"] == h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: a request for more exits at once with a message, before any GPU use
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_bench_lists_every_workload_it_runs():
+    import importlib.util
+    import inspect
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    src = inspect.getsource(bench.run_other)
+    for name in bench.OTHER_WORKLOADS:
+        assert f'name == "{name}"' in src, name
