@@ -11,6 +11,15 @@
  * electric-flow definition of Section 6.3 and the potential estimate of
  * Algorithm 5.
  *
+ * Entry points: graphs (rd_init_graph, rd_set_weights, rd_graph_info,
+ * rd_free_graph); Algorithm 3 for one pair (rd_query, and rd_query_trace for
+ * its coefficients) or many (rd_query_batch, with rd_tune_width and
+ * rd_batch_schedule for its launch shape); the edge-weight gradient
+ * (rd_grad_edges); potentials (rd_potentials); the Power Method of Algorithm 1
+ * (rd_power_method); Lanczos Push of Algorithm 4 (rd_lanczos_push); extreme
+ * Ritz values and the condition-number estimate (rd_ritz_bounds);
+ * diagnostics (rd_kernel_stats, rd_status_string, rd_last_error).
+ *
  * Conventions shared by every entry point:
  *  - Every call returns rd_status; nothing throws across the ABI. A handle is
  *    not thread-safe: calls on one handle must not overlap.
