@@ -473,10 +473,14 @@ def run_other(name, args):
                      lanczos_batched_fp64={"value": round(bq, 2), "unit": "queries/s",
                                            "speedup_over_power_method": round(bq * pdt / len(s), 1)},
                      roofline={"kernel": "k_pm_small (all steps of a pair in one workgroup, vectors in LDS)",
-                               "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                               "bound": "alu",
+                               "achieved": round(len(s) * l_pm * (4.0 * g.m + 3.0 * g.n) / pdt / 1e12, 4),
+                               "peak": 78.6, "unit": "TFLOP/s",
+                               "frac": round(len(s) * l_pm * (4.0 * g.m + 3.0 * g.n) / pdt / 1e12 / 78.6, 5),
                                "traffic": None, "avg_launch_ms": round(pdt * 1e3, 3), "launches": 1,
-                               "note": "LDS-resident: no HBM traffic per step; see the 64x64 grid line for "
-                                       "the batched-product roofline"},
+                               "note": "FP64 flops per step and pair: 2 per adjacency entry, 3 per node, against "
+                                       "the FP64 vector peak; LDS-resident, bound by LDS latency and the "
+                                       "per-step barrier, not by arithmetic"},
                      cpu_baseline={"value": round(1.0 / osec, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
                                    "sample": "1 pair, numpy Algorithm 1 with the same l"},
                      parity={"max_rel_err_vs_oracle": abs(float(out["r"][0]) - v0) / v0,
