@@ -559,22 +559,29 @@ def run_other(name, args):
                               f"products per pair (the least l, to within {max(16, l_pm // 64)}, whose results "
                               f"are all within {target:g} of batched Lanczos at 1e-12)"},
                      batched_product_path={"value": round(len(s) / gdt, 3), "unit": "queries/s",
-                                           "max_abs_diff_vs_value_path": float(np.max(np.abs(gout["r"] - out["r"])))},
+                                           "max_abs_diff_vs_value_path": float(np.max(np.abs(gout["r"] - out["r"]))),
+                                           "roofline": {"kernel": "k_spmm_short (width 128)", "bound": "hbm",
+                                                        "achieved": round(b / (avg * 1e-3) / 1e9, 1) if nl else None,
+                                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                        "avg_launch_ms": round(avg, 4), "launches": nl,
+                                                        "alg_bytes_per_launch": b,
+                                                        "note": "4,096-node graph: L2-resident; 64 wavefronts per "
+                                                                "product launch, latency-bound"}},
                      iterations={"power_method_l": l_pm, "lanczos_mean_k": float(lz["iters"].mean()),
                                  "lanczos_max_k": int(lz["iters"].max()),
                                  "ratio_l_over_k": round(l_pm / float(lz["iters"].mean()), 1),
                                  "kappa": round(kappa, 1), "sqrt_kappa": round(float(np.sqrt(kappa)), 1)},
                      lanczos_batched_fp64={"value": round(bq, 2), "unit": "queries/s",
                                            "speedup_over_power_method": round(bq * pdt / len(s), 1)},
-                     roofline={"kernel": "k_spmm_short (the Power Method step on the batched product, width 128; "
-                                         "the value path runs from LDS)",
-                               "bound": "hbm", "achieved": round(b / (avg * 1e-3) / 1e9, 1) if nl else None,
-                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if nl else None,
-                               "traffic": None, "avg_launch_ms": round(avg, 4), "launches": nl,
-                               "alg_bytes_per_launch": b,
-                               "note": "4,096-node graph: L2-resident; 64 wavefronts per product launch, "
-                                       "latency-bound"},
+                     roofline={"kernel": "k_pm_small (all steps of a pair in one workgroup, vectors in LDS)",
+                               "bound": "alu",
+                               "achieved": round(len(s) * l_pm * (4.0 * g.m + 3.0 * g.n) / pdt / 1e12, 4),
+                               "peak": 78.6, "unit": "TFLOP/s",
+                               "frac": round(len(s) * l_pm * (4.0 * g.m + 3.0 * g.n) / pdt / 1e12 / 78.6, 5),
+                               "traffic": None, "avg_launch_ms": round(pdt * 1e3, 3), "launches": 1,
+                               "note": "FP64 flops per step and pair: 2 per adjacency entry, 3 per node, against "
+                                       "the FP64 vector peak; LDS-resident, bound by LDS latency and the "
+                                       "per-step barrier, not by arithmetic"},
                      cpu_baseline={"value": round(k / secs, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
                                    "sample": f"{k} of the 100 pairs, numpy Algorithm 1 with the same l"},
                      parity={"max_rel_err_vs_oracle": float(np.max(np.abs(out["r"][:k] - np.array(vals)) / np.array(vals))),
