@@ -345,7 +345,7 @@ def run_other(name, args):
         from threadpoolctl import threadpool_limits
         from oracle import push as LPO
         W, d = LPO._adjacency(g)
-        perr, touched, pushes, secs = [], [], [], 0.0
+        perr, touched, pushes, raw_pushes, secs = [], [], [], [], 0.0
         with threadpool_limits(limits=1):
             for p in range(2):
                 t1 = time.time()
@@ -354,6 +354,7 @@ def run_other(name, args):
                 perr.append(abs(out["r"][p] - run.r) / abs(run.r))
                 touched.append(run.touched / g.n)
                 pushes.append(run.pushes / (k * 2.0 * g.m))
+                raw_pushes.append(run.pushes)
         line = _line("queries/s", len(s) / pdt, 1, 1, pdt * 1e3, "f64",
                      {"workload": name, "n": g.n, "m": g.m, "pairs": 256, "k": k, "eps_push": eps,
                       "path": "rd_lanczos_push: one workgroup per pair, frontier lists over per-slot node arrays"},
@@ -362,6 +363,16 @@ def run_other(name, args):
                      push_vs_lanczos_same_k={"max_rel_diff": float(np.max(np.abs(out["r"] - lz["r"]) / lz["r"])),
                                              "median_rel_diff": float(np.median(np.abs(out["r"] - lz["r"]) / lz["r"]))},
                      locality={"nodes_touched_share": touched, "edge_pushes_share_of_k_full_products": pushes},
+                     roofline={"kernel": "k_push (one 1024-thread workgroup per pair, all k iterations)",
+                               "bound": "hbm",
+                               "achieved": round(len(s) * float(np.mean(raw_pushes)) * 36.0 / pdt / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(len(s) * float(np.mean(raw_pushes)) * 36.0 / pdt / 1e9 / HBM_PEAK_GBS, 5),
+                               "traffic": None, "avg_launch_ms": round(pdt * 1e3, 3), "launches": 1,
+                               "note": "algorithmic bytes: 36 per edge push (index, degree and flag in the target "
+                                       "pass; index, value and degree in the pull), pushes per pair estimated "
+                                       "from the oracle's counts on the sample pairs; random accesses, bound by "
+                                       "their latency and the barriers between phases"},
                      cpu_baseline={"value": round(2 / secs, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
                                    "sample": "2 pairs, numpy Algorithm 4 with the same k and eps"},
                      parity={"max_rel_err_vs_oracle": float(max(perr))})
@@ -385,6 +396,8 @@ def run_other(name, args):
             dt = time.time() - t0
             _, hi2, _ = G.ritz_bounds(int(s[0]), int(t[0]), k // 2)
             ms, nl, b = G.kernel_stats(1)
+            if gname == "road_like_2000x2000":
+                road_stats = (ms, nl, b)
             rows[gname] = {"k": it, "theta_min": lo, "theta_max": hi, "kappa_hat": round(2.0 / (1.0 - hi), 2),
                            "kappa_hat_at_k_over_2": round(2.0 / (1.0 - hi2), 2), "seconds": round(dt, 3),
                            "k_spmv_avg_ms": round(ms / max(nl, 1), 4)}
@@ -408,6 +421,12 @@ def run_other(name, args):
                      {"workload": name, "graphs": rows,
                       "path": "rd_ritz_bounds: k-step FP64 Lanczos from the pair (e_s, e_t) start vector with "
                               "the null direction deflated, extreme eigenvalues of T_k by Sturm bisection"},
+                     roofline={"kernel": "k_spmv (the plain FP64 product; road-like 2000x2000 run)", "bound": "hbm",
+                               "achieved": round(road_stats[2] / (road_stats[0] / road_stats[1] * 1e-3) / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(road_stats[2] / (road_stats[0] / road_stats[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "traffic": None, "avg_launch_ms": round(road_stats[0] / road_stats[1], 4),
+                               "launches": road_stats[1], "alg_bytes_per_launch": road_stats[2]},
                      cpu_baseline={"value": round(1.0 / osec, 3), "unit": "runs/s (64x64 grid, k = 400)", "cores": 1,
                                    "kind": "oracle", "sample": "one deflated numpy Algorithm 3 run with its Ritz values"},
                      parity={"grid_theta_max_abs_diff_vs_oracle": abs(c1["theta_max"] - float(th[-1])),
